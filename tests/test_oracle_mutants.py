@@ -1,0 +1,79 @@
+"""Plant plausible mistakes in copies of the oracle and check the pins catch them.
+
+Each mutant is the oracle's C source with one textual change (a flipped sign,
+a dropped or scaled carry, a wrong index or length, a transposed operand, an
+imprecise constant, a wrong level order), compiled with gcc into a temporary
+directory.  Every mutant must fail at least one pin of ``oracle_pins``; the
+pins run in a child process so that a mutant which corrupts memory fails
+loudly instead of taking the test runner down.  Everything here runs on the
+CPU.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+RUNNER = r"""
+import sys
+sys.path[:0] = [{root!r}, {here!r}]
+import oracle, oracle_pins
+orc = oracle.Oracle({lib!r})
+failed = []
+for pin in oracle_pins.ALL_PINS:
+    try:
+        pin(orc)
+    except Exception as e:
+        failed.append(pin.__name__)
+print("FAILED_PINS", ",".join(failed))
+"""
+
+MUTANTS = {
+    "detail_sign": ("out[(na + m) * so] = s * (x1 - x0);", "out[(na + m) * so] = s * (x0 - x1);"),
+    "carry_scaled": ("if (n & 1) out[pairs * so] = in[(n - 1) * si]; /* carry, unscaled    */",
+                     "if (n & 1) out[pairs * so] = s * in[(n - 1) * si];"),
+    "synthesis_phase_swap": ("out[(2 * m) * so] = s * (a - d);", "out[(2 * m) * so] = s * (a + d);"),
+    "synthesis_carry_scaled": ("if (n & 1) out[(n - 1) * so] = in[pairs * si]; /* carry, unscaled    */",
+                               "if (n & 1) out[(n - 1) * so] = s * in[pairs * si];"),
+    "recursion_floor": ("fast_analysis_level(tmp, 1, y, 1, cur);\n        cur = (cur + 1) / 2;",
+                        "fast_analysis_level(tmp, 1, y, 1, cur);\n        cur = cur / 2;"),
+    "synthesis_operands_transposed": ("const double a = in[m * si];\n        const double d = in[(na + m) * si];",
+                                      "const double d = in[m * si];\n        const double a = in[(na + m) * si];"),
+    "2d_sizes_transposed": ("ch = (ch + 1) / 2;\n        cw = (cw + 1) / 2;",
+                            "ch = (cw + 1) / 2;\n        cw = (ch + 1) / 2;"),
+    "2d_width_floor": ("ch = (ch + 1) / 2;\n        cw = (cw + 1) / 2;",
+                       "ch = (ch + 1) / 2;\n        cw = cw / 2;"),
+    "2d_inverse_sizes": ("lh[j] = (lh[j - 1] + 1) / 2;", "lh[j] = lh[j - 1] / 2;"),
+    "imprecise_constant": ("return sqrt(0.5);", "return 0.70710678;"),
+    "inverse_level_order": ("for (int j = levels; j >= 1; --j) {\n        const int64_t cur = len[j - 1];\n        memcpy(tmp, x, (size_t)cur * sizeof(double));",
+                            "for (int j = 1; j <= levels; ++j) {\n        const int64_t cur = len[j - 1];\n        memcpy(tmp, x, (size_t)cur * sizeof(double));"),
+    "direct_tap_sign": ("b1[0] = s;  b1[1] = -s;", "b1[0] = -s; b1[1] = s;"),
+    "direct_wrong_phase": ("out[m] = y0[2 * m + 1];", "out[m] = y0[2 * m];"),
+    "2d_row_skips_last": ("for (int64_t r = 0; r < ch; ++r) {            /* rows (width)   */",
+                          "for (int64_t r = 0; r < ch - 1; ++r) {            /* rows (width)   */"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    src = open(oracle._SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    mutated = src.replace(old, new, 1)
+    path_c = os.path.join(tmp_path, "mutant.c")
+    with open(path_c, "w") as f:
+        f.write(mutated)
+    lib = oracle.build(force=True, src=path_c, out=os.path.join(tmp_path, "libmutant.so"))
+    code = RUNNER.format(root=ROOT, here=HERE, lib=lib)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, OMP_NUM_THREADS="2"))
+    if r.returncode != 0:
+        return  # the mutant crashed or raised outside a pin: a loud failure
+    line = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED_PINS")][0]
+    caught = [t for t in line.split(" ", 1)[1].split(",") if t] if " " in line else []
+    assert caught, f"mutant {name} passed every pin"
