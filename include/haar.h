@@ -1,0 +1,194 @@
+/*
+ * haar.h -- C ABI of libhaar, the fast (polyphase) Haar wavelet transform
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The transform (Ashok et al., "The Fast Haar Wavelet Transform for Signal &
+ * Image Processing"):
+ *   analysis bank, Sec. III, Eq. (11)-(12), Fig. 4: the input is split into
+ *   its two polyphase components first and only the decimated outputs are
+ *   computed; every pair (x0, x1) = (x[2m], x[2m+1]) gives
+ *       a[m] = (x0 + x1) / sqrt2,      d[m] = (x1 - x0) / sqrt2;
+ *   synthesis bank, Sec. IV, Eq. (19), Fig. 7: the exact inverse,
+ *       x[2m] = (a[m] - d[m]) / sqrt2, x[2m+1] = (a[m] + d[m]) / sqrt2;
+ *   Fig. 8: the two together reconstruct the input exactly.
+ * Multi-level transforms recurse on the approximation (dyadic), and 2D
+ * transforms apply one level along every row (width) of the current LL
+ * region and then along every column (height).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every data pointer is a DEVICE pointer on the current HIP device,
+ *   allocated and owned by the caller.  Tensors are contiguous, row-major and
+ *   batch-major: 1D [batch][length], 2D [batch][height][width].
+ * Layout.  Outputs have the shape of the inputs ("packed Mallat" layout).
+ *   1D: [a_L | d_L | d_{L-1} | ... | d_1] with |a_j| = ceil(n_{j-1}/2),
+ *   |d_j| = floor(n_{j-1}/2), n_0 = length.  2D, per level on the current
+ *   h x w LL region: LL = rows [0, ceil(h/2)) x cols [0, ceil(w/2)),
+ *   HL (high along width) = rows [0, ceil(h/2)) x cols [ceil(w/2), w),
+ *   LH (high along height) = rows [ceil(h/2), h) x cols [0, ceil(w/2)),
+ *   HH = the rest; the next level works on LL.
+ * Odd lengths.  When a level sees an odd count, its last sample passes
+ *   unscaled into the approximation and has no detail (the transform stays
+ *   orthonormal; it equals the usual Haar transform when 2^L divides the
+ *   size).
+ * Types.  dtype selects the STORAGE type of input and output (haar_dtype).
+ *   Arithmetic is always FP32 (the approximation path carries a compensated
+ *   FP32 pair); reduced-precision results are rounded to nearest even.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Calls are asynchronous: they enqueue kernels and return; they
+ *   never synchronise.  Device faults surface at the caller's next
+ *   synchronisation.
+ * Errors.  Every function returns a haar_status.  Argument checks run before
+ *   any HIP call, so an invalid call enqueues nothing.  On a non-OK return,
+ *   haar_last_error() holds a message (thread-local).
+ * Aliasing.  Out-of-place only: overlapping input and output ranges return
+ *   HAAR_ERR_ALIAS (the fused tiles write into other tiles' input ranges).
+ * Levels.  0 <= levels <= haar_max_levels_1d(length) (1D) or
+ *   haar_max_levels_2d(height, width) (2D); levels = 0 copies.  batch = 0
+ *   enqueues nothing and returns HAAR_OK.
+ * Threading.  All entry points are reentrant; the tuning table is guarded by
+ *   a mutex.
+ * Scratch.  Transforms deeper than one fused pass (2D levels > 5; 1D levels
+ *   beyond the on-chip depth of one work-group) keep intermediate
+ *   approximations in stream-ordered scratch obtained with hipMallocAsync on
+ *   `stream` and released with hipFreeAsync on the same stream.
+ */
+#ifndef HAAR_H_
+#define HAAR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HAAR_F32 = 0,   /* IEEE binary32 storage               */
+    HAAR_BF16 = 1,  /* bfloat16 storage, FP32 arithmetic    */
+    HAAR_F16 = 2    /* IEEE binary16 storage, FP32 arithmetic */
+} haar_dtype;
+
+typedef enum {
+    HAAR_OK = 0,
+    HAAR_ERR_NULL = 1,        /* a required pointer is NULL                        */
+    HAAR_ERR_DTYPE = 2,       /* dtype is not a haar_dtype                         */
+    HAAR_ERR_SHAPE = 3,       /* a size < 1, batch < 0, or a size too large        */
+    HAAR_ERR_LEVELS = 4,      /* levels outside [0, max levels]                   */
+    HAAR_ERR_ALIAS = 5,       /* input and output byte ranges overlap              */
+    HAAR_ERR_WORKSPACE = 6,   /* workspace NULL, too small or misaligned           */
+    HAAR_ERR_HIP = 7,         /* a HIP runtime call failed (see haar_last_error)   */
+    HAAR_ERR_PLAN = 8,        /* NULL / not uploaded plan, or an invalid plan item */
+    HAAR_ERR_UNSUPPORTED = 9  /* valid arguments this build does not implement     */
+} haar_status;
+
+/* ------------------------------------------------------------------------
+ * Plain transforms.
+ * ------------------------------------------------------------------------ */
+
+/* Multi-level 1D analysis (Sec. III, Eq. (11)-(12), Fig. 4, recursed on the
+ * approximation).  x: [batch][length] input, y: [batch][length] output in
+ * the packed layout.  Both device pointers, caller-owned, not overlapping. */
+int haar_fwd_1d(const void* x, void* y, int64_t length, int32_t levels,
+                int64_t batch, int32_t dtype, void* stream);
+
+/* Multi-level 1D synthesis (Sec. IV, Eq. (19), Fig. 7): the exact inverse
+ * (and, the transform being orthonormal, the adjoint) of haar_fwd_1d.
+ * y: packed coefficients [batch][length], x: reconstruction. */
+int haar_inv_1d(const void* y, void* x, int64_t length, int32_t levels,
+                int64_t batch, int32_t dtype, void* stream);
+
+/* Multi-level separable 2D analysis (rows, then columns, per level; Fig. 4
+ * along each axis; the lowpass image of Sec. V is the LL band).
+ * x: [batch][height][width], y: same shape, packed quadrant layout. */
+int haar_fwd_2d(const void* x, void* y, int64_t height, int64_t width,
+                int32_t levels, int64_t batch, int32_t dtype, void* stream);
+
+/* Multi-level separable 2D synthesis: exact inverse / adjoint of
+ * haar_fwd_2d (columns, then rows, per level, from level L down to 1). */
+int haar_inv_2d(const void* y, void* x, int64_t height, int64_t width,
+                int32_t levels, int64_t batch, int32_t dtype, void* stream);
+
+/* ceil(log2(length)) for length >= 1 (0 for length 1); -1 if length < 1.
+ * Beyond this depth every further level would be a no-op. */
+int haar_max_levels_1d(int64_t length);
+
+/* ceil(log2(max(height, width))); -1 if a size < 1. */
+int haar_max_levels_2d(int64_t height, int64_t width);
+
+/* ------------------------------------------------------------------------
+ * Batched transforms of uneven sizes: one persistent launch per execute.
+ * A plan holds host memory only.  Its device-side descriptor table and
+ * counters live in a caller-owned workspace of haar_plan_workspace_size()
+ * bytes (256-byte aligned).  haar_plan_upload() writes the table and zeroes
+ * the counters (it enqueues copies: not allowed during stream capture);
+ * haar_plan_execute() enqueues exactly one kernel, allocates nothing, never
+ * synchronises and leaves the counters at zero when the kernel ends, so it
+ * may be captured into a hipGraph and replayed.  Executions that share one
+ * workspace must not overlap in time.  Item pointers are device pointers;
+ * every item must satisfy the plain-call rules above (no aliasing).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const void* in;   /* [length] input (device)          */
+    void* out;        /* [length] output (device)         */
+    int64_t length;
+    int32_t levels;   /* 0 .. haar_max_levels_1d(length)  */
+} haar_item_1d;
+
+typedef struct {
+    const void* in;   /* [height][width] input (device)   */
+    void* out;        /* [height][width] output (device)  */
+    int64_t height;
+    int64_t width;
+    int32_t levels;   /* 0 .. min(5, haar_max_levels_2d)  */
+} haar_item_2d;
+
+typedef struct haar_plan haar_plan;
+
+/* inverse = 0: analysis of every item; inverse = 1: synthesis. */
+int haar_plan_create_1d(const haar_item_1d* items, int64_t count, int32_t dtype,
+                        int32_t inverse, haar_plan** out);
+int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype,
+                        int32_t inverse, haar_plan** out);
+int haar_plan_workspace_size(const haar_plan* plan, size_t* bytes);
+int haar_plan_upload(haar_plan* plan, void* workspace, void* stream);
+int haar_plan_execute(const haar_plan* plan, void* workspace, void* stream);
+/* Number of work tiles and the persistent grid size (work-groups). */
+int haar_plan_info(const haar_plan* plan, int64_t* tiles, int32_t* grid);
+int haar_plan_destroy(haar_plan* plan);
+
+/* ------------------------------------------------------------------------
+ * Tuning.  haar_tune_2d times the candidate tile shapes for one problem on
+ * `stream` (hipEvents; it synchronises that stream) using caller-owned
+ * device scratch of at least 2 * batch * height * width * element bytes,
+ * records the fastest in the process-wide table and returns its index in
+ * *choice.  The table is consulted by later plain calls and plans with the
+ * same (dtype, direction, levels, size class).  haar_tune_save/load write
+ * and read the table as JSON text.  Never call these during capture.
+ * ------------------------------------------------------------------------ */
+int haar_tune_2d(int32_t dtype, int32_t inverse, int64_t height, int64_t width,
+                 int32_t levels, int64_t batch, void* scratch, size_t scratch_bytes,
+                 void* stream, int32_t* choice);
+/* Same for the 1D chunk shapes (scratch: 2 * batch * length * element bytes). */
+int haar_tune_1d(int32_t dtype, int32_t inverse, int64_t length, int32_t levels, int64_t batch,
+                 void* scratch, size_t scratch_bytes, void* stream, int32_t* choice);
+int haar_tune_save(const char* path);
+int haar_tune_load(const char* path);
+/* Number of 2D tile-shape candidates and a description of candidate i. */
+int haar_tune_candidates_2d(int32_t dtype);
+const char* haar_tune_candidate_name(int32_t dtype, int32_t index);
+/* Force candidate `index` (or -1 to restore table/default choice) for 2D. */
+int haar_force_config_2d(int32_t dtype, int32_t index);
+
+/* ------------------------------------------------------------------------
+ * Diagnostics.
+ * ------------------------------------------------------------------------ */
+const char* haar_status_string(int status);
+const char* haar_last_error(void);
+const char* haar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAAR_H_ */

@@ -1,0 +1,230 @@
+// Device helpers for the Haar kernels: storage formats and compensated FP32.
+//
+// Storage types are read into FP32 registers and written back with
+// round-to-nearest-even; all arithmetic is FP32.  The approximation path of
+// the analysis bank carries an unevaluated pair (hi + lo) so that the sums of
+// the polyphase components (Eq. (11)) are kept to about 48 bits across the
+// fused levels and rounded once at the end.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace haar {
+
+constexpr double kRsqrt2 = 0.70710678118654752440084436210485;   // b00 = a00
+constexpr double kSqrt2 = 1.4142135623730950488016887242097;
+constexpr float kRs2Hi = (float)kRsqrt2;
+constexpr float kRs2Lo = (float)(kRsqrt2 - (double)(float)kRsqrt2);
+constexpr float kS2Hi = (float)kSqrt2;
+constexpr float kS2Lo = (float)(kSqrt2 - (double)(float)kSqrt2);
+
+// ---------------------------------------------------------------------------
+// Pair arithmetic (Knuth's TwoSum, Dekker's FastTwoSum, FMA product error).
+// ---------------------------------------------------------------------------
+struct df {
+    float hi, lo;
+};
+
+__device__ __forceinline__ df two_sum(float a, float b) {
+    const float s = a + b;
+    const float bb = s - a;
+    const float e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+
+__device__ __forceinline__ df fast_two_sum(float a, float b) {   // |a| >= |b|
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ df df_from(float a) { return {a, 0.0f}; }
+
+__device__ __forceinline__ df df_add(df a, df b) {
+    const df s = two_sum(a.hi, b.hi);
+    return fast_two_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+
+// (a + b + c + d) of four exact floats
+__device__ __forceinline__ df df_sum4f(float a, float b, float c, float d) {
+    const df s1 = two_sum(a, b);
+    const df s2 = two_sum(c, d);
+    const df s = two_sum(s1.hi, s2.hi);
+    return fast_two_sum(s.hi, s.lo + (s1.lo + s2.lo));
+}
+
+__device__ __forceinline__ df df_sum4(df a, df b, df c, df d) {
+    const df s1 = two_sum(a.hi, b.hi);
+    const df s2 = two_sum(c.hi, d.hi);
+    const df s = two_sum(s1.hi, s2.hi);
+    const float lo = (s.lo + (s1.lo + s2.lo)) + ((a.lo + b.lo) + (c.lo + d.lo));
+    return fast_two_sum(s.hi, lo);
+}
+
+__device__ __forceinline__ df df_scale(df a, float p2) {   // exact for a power of two
+    return {a.hi * p2, a.lo * p2};
+}
+
+// a * (c_hi + c_lo)
+__device__ __forceinline__ df df_mul(df a, float c_hi, float c_lo) {
+    const float p = a.hi * c_hi;
+    const float e = __builtin_fmaf(a.hi, c_hi, -p);
+    const float lo = e + (a.hi * c_lo + a.lo * c_hi);
+    return fast_two_sum(p, lo);
+}
+
+__device__ __forceinline__ df df_rs2(df a) { return df_mul(a, kRs2Hi, kRs2Lo); }
+__device__ __forceinline__ df df_s2(df a) { return df_mul(a, kS2Hi, kS2Lo); }
+
+__device__ __forceinline__ float df_round(df a) { return a.hi + a.lo; }
+
+// b - a, rounded once (both pairs)
+__device__ __forceinline__ float df_diff(df b, df a) {
+    return (b.hi - a.hi) + (b.lo - a.lo);
+}
+
+// 2^(-j/2) as a pair (exact power of two for even j)
+__device__ __forceinline__ df pow2_half_neg(int j, float& p2) {
+    p2 = __builtin_ldexpf(1.0f, -(j >> 1));
+    if (j & 1) return {kRs2Hi * p2, kRs2Lo * p2};
+    return {p2, 0.0f};
+}
+
+// S * 2^(-j/2) rounded once: the normalised approximation from a sum of
+// 2^j samples.
+__device__ __forceinline__ float df_norm(df s, int j) {
+    const float p2 = __builtin_ldexpf(1.0f, -(j >> 1));
+    if (j & 1) return df_round(df_mul(df_scale(s, p2), kRs2Hi, kRs2Lo));
+    return df_round(df_scale(s, p2));
+}
+
+// single float times 2^(-j/2)
+__device__ __forceinline__ float f_norm(float d, int j) {
+    const float p2 = __builtin_ldexpf(1.0f, -(j >> 1));
+    return (j & 1) ? (d * p2) * kRs2Hi : d * p2;
+}
+
+// ---------------------------------------------------------------------------
+// Storage formats.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct StF32 {
+    using raw = float;
+    static constexpr int kBytes = 4;
+    __device__ __forceinline__ static float ld(raw v) { return v; }
+    __device__ __forceinline__ static raw st(float f) { return f; }
+};
+
+struct StBF16 {
+    using raw = uint16_t;
+    static constexpr int kBytes = 2;
+    __device__ __forceinline__ static float ld(raw v) { return __uint_as_float((uint32_t)v << 16); }
+    __device__ __forceinline__ static raw st(float f) { return f32_to_bf16_rne(f); }
+};
+
+struct StF16 {
+    using raw = uint16_t;
+    static constexpr int kBytes = 2;
+    __device__ __forceinline__ static float ld(raw v) {
+        return (float)__builtin_bit_cast(_Float16, v);
+    }
+    __device__ __forceinline__ static raw st(float f) {
+        return __builtin_bit_cast(uint16_t, (_Float16)f);
+    }
+};
+
+// Load N consecutive elements (N * kBytes in {2, 4, 8, 16}, pointer aligned
+// to that size) into floats.
+template <class S, int N>
+__device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
+    constexpr int B = N * S::kBytes;
+    static_assert(B == 2 || B == 4 || B == 8 || B == 16, "vector width");
+    if constexpr (S::kBytes == 4) {
+        if constexpr (N == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(p);
+            out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+        } else if constexpr (N == 2) {
+            const float2 v = *reinterpret_cast<const float2*>(p);
+            out[0] = v.x; out[1] = v.y;
+        } else {
+            out[0] = p[0];
+        }
+    } else {
+        uint32_t w[B >= 4 ? B / 4 : 1];
+        if constexpr (B == 16) {
+            const uint4 v = *reinterpret_cast<const uint4*>(p);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else if constexpr (B == 8) {
+            const uint2 v = *reinterpret_cast<const uint2*>(p);
+            w[0] = v.x; w[1] = v.y;
+        } else if constexpr (B == 4) {
+            w[0] = *reinterpret_cast<const uint32_t*>(p);
+        } else {
+            out[0] = S::ld(p[0]);
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < N / 2; ++i) {
+            out[2 * i] = S::ld((uint16_t)(w[i] & 0xffffu));
+            out[2 * i + 1] = S::ld((uint16_t)(w[i] >> 16));
+        }
+    }
+}
+
+template <class S, int N>
+__device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {
+    constexpr int B = N * S::kBytes;
+    static_assert(B == 2 || B == 4 || B == 8 || B == 16, "vector width");
+    if constexpr (S::kBytes == 4) {
+        if constexpr (N == 4) {
+            *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+        } else if constexpr (N == 2) {
+            *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+        } else {
+            p[0] = v[0];
+        }
+    } else {
+        if constexpr (B == 2) {
+            p[0] = S::st(v[0]);
+        } else {
+            uint32_t w[B / 4];
+#pragma unroll
+            for (int i = 0; i < N / 2; ++i)
+                w[i] = (uint32_t)S::st(v[2 * i]) | ((uint32_t)S::st(v[2 * i + 1]) << 16);
+            if constexpr (B == 16) {
+                *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+            } else if constexpr (B == 8) {
+                *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+            } else {
+                *reinterpret_cast<uint32_t*>(p) = w[0];
+            }
+        }
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void st1(typename S::raw* p, float v) { *p = S::st(v); }
+
+template <class S>
+__device__ __forceinline__ float ld1(const typename S::raw* p) { return S::ld(*p); }
+
+// ceil(n / 2^j)
+__device__ __forceinline__ int64_t ceil_shift(int64_t n, int j) {
+    return (n + ((int64_t)1 << j) - 1) >> j;
+}
+
+// Map a block index to a tile index so that the tiles handled by one XCD
+// (blocks are dealt round-robin to the 8 XCDs) form one contiguous range.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
+    const int64_t q = total >> 3, r = total & 7;
+    const int64_t x = b & 7, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+}  // namespace haar

@@ -1,0 +1,30 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace haar {
+
+inline int elem_bytes(int dtype) { return dtype == 0 ? 4 : 2; }
+
+int set_error(int code, const char* fmt, ...);
+int hip_error(hipError_t e, const char* what);
+int max_levels(int64_t n);
+bool aligned(const void* p, int a);
+
+// HAAR_FAULT_INJECT=launch makes every transform call fail as if its launch
+// had failed (HAAR_ERR_HIP) before anything is enqueued: a host-side way to
+// exercise the error path of callers.
+int fault_injected();
+
+// Tile / chunk configuration chosen for a problem (tuning table or default).
+int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels);
+int choose_config_1d(int dtype, bool inverse, int64_t n, int levels);
+
+int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch, int dtype,
+           bool inverse, hipStream_t s, int cfg_override);
+int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype, bool inverse,
+           hipStream_t s, int cfg_override);
+
+}  // namespace haar

@@ -1,0 +1,139 @@
+"""C-ABI checks that need no GPU: symbols, argument validation, error paths, tuning table I/O.
+
+Every call here either fails validation (which runs before any HIP call) or
+is a host-only function, so nothing is enqueued on a device.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "haar.h")
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1002_2184_amd import build as B
+    B.build(force=False)
+    from paper_1002_2184_amd import _abi
+    return _abi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(haar_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(abi):
+    names = declared_functions()
+    assert len(names) >= 20, names
+    lib = ctypes.CDLL(abi.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in haar.h but not exported"
+    assert set(names) == set(abi.exported_names()), "binding and header disagree"
+
+
+def test_binding_has_same_names(abi):
+    for n in declared_functions():
+        assert callable(getattr(abi, n)), n
+
+
+def test_max_levels(abi):
+    assert abi.haar_max_levels_1d(1) == 0
+    assert abi.haar_max_levels_1d(2) == 1
+    assert abi.haar_max_levels_1d(65536) == 16
+    assert abi.haar_max_levels_1d(65537) == 17
+    assert abi.haar_max_levels_1d(0) == -1
+    assert abi.haar_max_levels_2d(4096, 4096) == 12
+    assert abi.haar_max_levels_2d(3, 1000) == 10
+    assert abi.haar_max_levels_2d(0, 5) == -1
+
+
+X, Y = 0x10000000, 0x20000000     # fake, non-overlapping device addresses (never dereferenced)
+
+
+@pytest.mark.parametrize("call,code", [
+    (lambda a: a.haar_fwd_1d(X, Y, 16, 2, 1, 7, 0), 2),          # dtype
+    (lambda a: a.haar_fwd_1d(X, Y, 0, 0, 1, 0, 0), 3),           # length < 1
+    (lambda a: a.haar_fwd_1d(X, Y, 16, 2, -1, 0, 0), 3),         # batch < 0
+    (lambda a: a.haar_fwd_1d(X, Y, 16, 5, 1, 0, 0), 4),          # levels > log2
+    (lambda a: a.haar_inv_1d(X, Y, 16, -1, 1, 0, 0), 4),         # levels < 0
+    (lambda a: a.haar_fwd_1d(0, Y, 16, 2, 1, 0, 0), 1),          # NULL input
+    (lambda a: a.haar_inv_1d(X, 0, 16, 2, 1, 0, 0), 1),          # NULL output
+    (lambda a: a.haar_fwd_1d(X, X + 8, 16, 2, 1, 0, 0), 5),      # overlap
+    (lambda a: a.haar_fwd_2d(X, Y, 0, 8, 1, 1, 0, 0), 3),
+    (lambda a: a.haar_fwd_2d(X, Y, 8, 8, 4, 1, 0, 0), 4),
+    (lambda a: a.haar_inv_2d(X, Y, 8, 8, 1, 1, 3, 0), 2),
+    (lambda a: a.haar_inv_2d(X, X, 8, 8, 1, 1, 0, 0), 5),        # in place
+    (lambda a: a.haar_fwd_2d(X, Y, 1 << 40, 1 << 40, 1, 1, 0, 0), 3),   # size overflow
+])
+def test_validation_codes(abi, call, code):
+    assert call(abi) == code
+    assert abi.haar_last_error() != ""
+
+
+def test_overlap_detects_tail(abi, monkeypatch):
+    # 8x8 f32 = 256 bytes: an output starting inside the input range overlaps
+    assert abi.haar_fwd_2d(X, X + 252, 8, 8, 1, 1, 0, 0) == 5
+    assert abi.haar_fwd_2d(X + 252, X, 8, 8, 1, 1, 0, 0) == 5
+    # bf16: 128 bytes, so +128 does not overlap and passes validation; the
+    # fault hook stops the call before anything is enqueued (fake pointers)
+    monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")
+    assert abi.haar_fwd_2d(X, X + 128, 8, 8, 1, 1, 1, 0) == 7
+
+
+def test_batch_zero_is_a_noop(abi):
+    assert abi.haar_fwd_1d(0, 0, 16, 2, 0, 0, 0) == 0
+    assert abi.haar_inv_2d(0, 0, 8, 8, 3, 0, 1, 0) == 0
+
+
+def test_fault_injection_maps_to_hip_error(abi, monkeypatch):
+    monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")
+    assert abi.haar_fwd_2d(X, Y, 64, 64, 3, 1, 0, 0) == 7
+    assert "injected" in abi.haar_last_error()
+    assert abi.haar_inv_1d(X, Y, 64, 3, 2, 1, 0) == 7
+
+
+def test_status_strings(abi):
+    assert abi.haar_status_string(0) == "HAAR_OK"
+    assert abi.haar_status_string(5) == "HAAR_ERR_ALIAS"
+    assert abi.haar_status_string(99) == "HAAR_ERR_UNKNOWN"
+    assert "gfx950" in abi.haar_version()
+
+
+def test_python_check_raises(abi):
+    with pytest.raises(abi.HaarError) as ei:
+        abi.check(abi.haar_fwd_1d(X, Y, 16, 9, 1, 0, 0))
+    assert ei.value.status == 4
+
+
+def test_tuning_table_roundtrip(abi, tmp_path):
+    src = tmp_path / "in.json"
+    src.write_text('{\n  "format": "libhaar-tuning-1",\n  "2d:f32:fwd:L5:h12:w12": 2,\n'
+                   '  "1d:bf16:inv:L10:n10": 3,\n  "2d:f32:fwd:L1:h1:w1": 99\n}\n')
+    assert abi.haar_tune_load(str(src)) == 0
+    out = tmp_path / "out.json"
+    assert abi.haar_tune_save(str(out)) == 0
+    text = out.read_text()
+    assert '"2d:f32:fwd:L5:h12:w12": 2' in text
+    assert '"1d:bf16:inv:L10:n10": 3' in text
+    assert "99" not in text                       # out-of-range index rejected
+    bad = tmp_path / "bad.json"
+    bad.write_text("not a tuning file")
+    assert abi.haar_tune_load(str(bad)) == 9
+    assert abi.haar_tune_load(str(tmp_path / "missing.json")) == 9
+
+
+def test_tuning_validation(abi):
+    choice = ctypes.c_int32(-1)
+    assert abi.haar_tune_2d(0, 0, 64, 64, 3, 1, 0, 0, 0, ctypes.byref(choice)) == 1
+    assert abi.haar_tune_2d(0, 0, 64, 64, 9, 1, X, 1 << 20, 0, ctypes.byref(choice)) == 4
+    assert abi.haar_tune_2d(0, 0, 64, 64, 3, 1, X, 100, 0, ctypes.byref(choice)) == 6
+    assert abi.haar_tune_1d(5, 0, 64, 3, 1, X, 1 << 20, 0, ctypes.byref(choice)) == 2
+    assert abi.haar_tune_candidates_2d(0) >= 2
+    assert "tile" in abi.haar_tune_candidate_name(0, 0)
+    assert abi.haar_force_config_2d(0, 99) == 9
+    assert abi.haar_force_config_2d(0, -1) == 0
