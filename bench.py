@@ -58,6 +58,86 @@ def load_traffic(kernel: str):
     return None if entry is None else entry.get("hbm_bytes_per_launch")
 
 
+def pmc_probe():
+    """Dispatches for rocprofv3 counter passes: a plain 64 MiB device copy (the
+    calibration reference of known size), then the fwd2d and inv2d kernels of
+    the benchmark workload, 8 of each, on rotating buffers."""
+    import torch
+    from paper_1002_2184_amd import transform as T
+    from workloads import generators as G
+    dev = torch.device("cuda", 0)
+    x0 = torch.from_numpy(G.config2(H, W)).to(dev)
+    xs = [x0.clone() for _ in range(SETS)]
+    ys = [torch.empty_like(x0) for _ in range(SETS)]
+    zs = [torch.empty_like(x0) for _ in range(SETS)]
+    for k in range(8):
+        ys[k % SETS].copy_(xs[k % SETS])
+    torch.cuda.synchronize()
+    for k in range(8):
+        s = k % SETS
+        T.fwd2d(xs[s], LEVELS, out=ys[s])
+        T.inv2d(ys[s], LEVELS, out=zs[s])
+    torch.cuda.synchronize()
+    print("pmc probe done", flush=True)
+
+
+def write_traffic(fetch_csv: str, write_csv: str, command: str):
+    """Turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) into HBM bytes per launch of fwd2d / inv2d, each counter scaled
+    by what it reads for the 64 MiB reference copy, and write the committed
+    summary (JSON for bench.py, Markdown for people)."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            key = ("copy" if "copyBuffer" in name or "copy_kernel" in name else
+                   "fwd2d" if "fwd2d_kernel" in name else "inv2d" if "inv2d_kernel" in name else None)
+            if key:
+                out.setdefault(key, []).append(float(r["Counter_Value"]))
+        return {k: statistics.median(v) for k, v in out.items()}
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    ref_kib = H * W * 4 / 1024.0
+    f_scale, w_scale = ref_kib / fetch["copy"], ref_kib / write["copy"]
+    alg = 2 * H * W * 4
+    kernels = {}
+    for k in ("fwd2d", "inv2d"):
+        rd = fetch[k] * f_scale * 1024.0
+        wr = write[k] * w_scale * 1024.0
+        kernels[k] = {"fetch_kib_raw": fetch[k], "write_kib_raw": write[k],
+                      "hbm_read_bytes": int(rd), "hbm_write_bytes": int(wr),
+                      "hbm_bytes_per_launch": int(rd + wr),
+                      "vs_algorithmic": round((rd + wr) / alg, 4)}
+    doc = {"workload": "2d-smooth-4096x4096-L5", "command": command,
+           "reference": {"kernel": "torch copy_ of 64 MiB (hipMemcpy device-to-device)",
+                         "fetch_kib_raw": fetch["copy"], "write_kib_raw": write["copy"],
+                         "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)},
+           "algorithmic_bytes_per_launch": alg,
+           "kernel_sources_sha256_16": kernel_hash(), "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(doc, f, indent=1)
+    md = TRAFFIC_FILE[:-5] + ".md"
+    with open(md, "w") as f:
+        f.write(f"# HBM traffic per launch, 4096x4096 FP32, 5 levels\n\nCommand: `{command}`\n\n")
+        f.write(f"Reference: 64 MiB device copy reads FETCH_SIZE = {fetch['copy']:.0f} KiB "
+                f"(scale {f_scale:.4f}) and WRITE_SIZE = {write['copy']:.0f} KiB (scale {w_scale:.4f}).\n\n")
+        f.write("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read MiB | HBM write MiB | total / algorithmic |\n")
+        f.write("|---|---|---|---|---|---|\n")
+        for k, v in kernels.items():
+            f.write(f"| {k} | {v['fetch_kib_raw']:.0f} | {v['write_kib_raw']:.0f} | "
+                    f"{v['hbm_read_bytes'] / 2**20:.2f} | {v['hbm_write_bytes'] / 2**20:.2f} | "
+                    f"{v['vs_algorithmic']:.4f} |\n")
+        f.write(f"\nKernel sources sha256[:16] = {kernel_hash()} (bench.py reports traffic only "
+                f"while the sources match).\n")
+    print(json.dumps(doc))
+
+
 def cpu_baseline(x_np, budget_s: float):
     """The FP64 oracle (fwd + inv of the same image) on this host's cores."""
     import numpy as np
@@ -85,7 +165,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run the dispatches profiled by the rocprofv3 counter passes and exit")
+    ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="summarise two rocprofv3 counter CSVs into the profiles/ traffic file")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
+    if args.pmc_probe:
+        pmc_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(the transform shards by batch items or row stripes without communication; "
@@ -126,33 +216,39 @@ def main():
         step(k)
     torch.cuda.synchronize()
 
-    # per-launch events over the timed region
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    # headline: K steps bracketed by events, nothing else in the stream
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
     for k in range(args.steps):
-        step(k, evs[k])
+        step(k)
     t_end.record(stream)
     torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
+    ms_step = t_start.elapsed_time(t_end) / args.steps
+    gbps = alg_step / (ms_step * 1e-3) / 1e9
+
+    # per-launch HIP events on the launch stream (same steps again)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        step(k, evs[k])
+    torch.cuda.synchronize()
     fwd_ms = [e[0].elapsed_time(e[1]) for e in evs]
     inv_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    ms_step = total_ms / args.steps
-    gbps = alg_step / (ms_step * 1e-3) / 1e9
 
     # correctness spot check of the timed outputs (GPU side)
     rt_err = float((zs[0] - xs[0]).abs().max() / xs[0].pow(2).mean().sqrt())
 
-    # autograd fwd + bwd (backward = synthesis on the upstream gradient)
-    g = torch.randn(H, W, device=dev)
+    # autograd fwd + bwd (backward = synthesis on the upstream gradient); the
+    # upstream gradients rotate with the inputs so every step reads cold data
+    gs = [torch.randn(H, W, device=dev) for _ in range(SETS)]
     xr = [x.clone().requires_grad_(True) for x in xs]
 
     def ag_step(k):
         s = k % SETS
         y = AG.HaarFwd2D.apply(xr[s], LEVELS)
-        (gx,) = torch.autograd.grad(y, xr[s], g)
+        (gx,) = torch.autograd.grad(y, xr[s], gs[s])
         return gx
 
     for k in range(args.warmup):

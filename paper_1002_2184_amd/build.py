@@ -48,14 +48,15 @@ def _stale() -> bool:
     return any(os.path.getmtime(d) > t for d in deps)
 
 
-def build(force: bool = True, jobs: int = 8, verbose: bool = False) -> str:
-    if not force and not _stale():
+def build(force: bool = True, jobs: int = 8, verbose: bool = False, defines=(), out: str = LIB) -> str:
+    """Compile and link; `defines` adds -D flags, `out` redirects the library."""
+    if not force and not _stale() and out == LIB and not defines:
         return LIB
     tmp = tempfile.mkdtemp(prefix="haarbuild_")
     try:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
-            cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+            cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", src, "-o", obj]
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
                 raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
@@ -65,15 +66,15 @@ def build(force: bool = True, jobs: int = 8, verbose: bool = False) -> str:
 
         with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
             objs = list(ex.map(compile_one, sources()))
-        out_tmp = LIB + f".tmp{os.getpid()}"
+        out_tmp = out + f".tmp{os.getpid()}"
         cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed:\n{r.stderr}")
-        os.replace(out_tmp, LIB)
+        os.replace(out_tmp, out)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    return LIB
+    return out
 
 
 def main():
@@ -81,8 +82,10 @@ def main():
     ap.add_argument("--force", action="store_true")
     ap.add_argument("-j", type=int, default=8)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("-D", action="append", default=[], help="extra preprocessor define")
+    ap.add_argument("-o", default=LIB, help="output library path")
     a = ap.parse_args()
-    print(build(force=a.force or True, jobs=a.j, verbose=a.v))
+    print(build(force=True, jobs=a.j, verbose=a.v, defines=a.D, out=a.o))
 
 
 if __name__ == "__main__":

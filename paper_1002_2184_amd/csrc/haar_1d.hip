@@ -341,7 +341,7 @@ template <class SX, class SD, class SL, int E, int NT>
 __global__ __launch_bounds__(NT) void fwd1d_kernel(Pass1D p) {
     using G = Geo1D<SX, E, NT>;
     __shared__ df sm[G::NW];
-    const bool remap = (int64_t)gridDim.x == p.total_chunks;
+    const bool remap = p.remap && (int64_t)gridDim.x == p.total_chunks;
     for (int64_t b = blockIdx.x; b < p.total_chunks; b += gridDim.x) {
         const int64_t c = remap ? xcd_tile(b, p.total_chunks) : b;
         const int64_t item = c / p.chunks_per_item, chunk = c - item * p.chunks_per_item;
@@ -358,7 +358,7 @@ template <class SX, class SD, class SL, int E, int NT>
 __global__ __launch_bounds__(NT) void inv1d_kernel(Pass1D p) {
     using G = Geo1D<SX, E, NT>;
     __shared__ float sm[G::NW * 8];
-    const bool remap = (int64_t)gridDim.x == p.total_chunks;
+    const bool remap = p.remap && (int64_t)gridDim.x == p.total_chunks;
     for (int64_t b = blockIdx.x; b < p.total_chunks; b += gridDim.x) {
         const int64_t c = remap ? xcd_tile(b, p.total_chunks) : b;
         const int64_t item = c / p.chunks_per_item, chunk = c - item * p.chunks_per_item;
@@ -375,22 +375,23 @@ __global__ __launch_bounds__(NT) void inv1d_kernel(Pass1D p) {
 // Chunk table and launchers.  Index -> (threads, elements per thread).
 // ---------------------------------------------------------------------------
 #define HAAR_1D_CHUNKS(X) \
-    X(0, 256, 16)         \
-    X(1, 1024, 16)        \
-    X(2, 64, 16)          \
-    X(3, 128, 16)
+    X(0, 256, 16, 1)      \
+    X(1, 1024, 16, 1)     \
+    X(2, 64, 16, 1)       \
+    X(3, 128, 16, 1)      \
+    X(4, 256, 16, 0)
 
-int num_chunk_configs_1d() { return 4; }
+int num_chunk_configs_1d() { return 5; }
 
 Chunk1D chunk_config_1d(int index) {
     switch (index) {
-#define X(I, NT_, E_) \
-    case I:           \
-        return Chunk1D{NT_, E_};
+#define X(I, NT_, E_, RM_) \
+    case I:                \
+        return Chunk1D{NT_, E_, RM_};
         HAAR_1D_CHUNKS(X)
 #undef X
         default:
-            return Chunk1D{256, 16};
+            return Chunk1D{256, 16, 1};
     }
 }
 
@@ -408,8 +409,8 @@ static hipError_t launch1d(const Pass1D& p, bool inverse, hipStream_t s) {
 template <class S>
 static hipError_t dispatch1d(const Pass1D& p, int cfg, bool inverse, hipStream_t s) {
     switch (cfg) {
-#define X(I, NT_, E_) \
-    case I:           \
+#define X(I, NT_, E_, RM_) \
+    case I:                \
         return launch1d<S, S, S, NT_, E_>(p, inverse, s);
         HAAR_1D_CHUNKS(X)
 #undef X
@@ -423,7 +424,7 @@ template <class S>
 static hipError_t dispatch1d_mixed(const Pass1D& p, int cfg, bool x_f32, bool ll_f32, bool inverse,
                                    hipStream_t s) {
     switch (cfg) {
-#define X(I, NT_, E_)                                                            \
+#define X(I, NT_, E_, RM_)                                                       \
     case I:                                                                      \
         if (x_f32 && ll_f32) return launch1d<StF32, S, StF32, NT_, E_>(p, inverse, s); \
         if (x_f32) return launch1d<StF32, S, S, NT_, E_>(p, inverse, s);                \

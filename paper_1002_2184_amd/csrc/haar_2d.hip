@@ -100,6 +100,10 @@ struct Geo2D {
     static constexpr int AN = (TH / 4) * (TW / 4);   // LDS buffer A: LL2 region
     static constexpr int BN = (TH / 8) * (TW / 8);   // LDS buffer B: LL3 region
     static constexpr int SMEM = 2 * AN + 2 * BN;     // floats (hi + lo each)
+    // synthesis: LL_L and the detail bands of levels 3..L (L <= 5) of one tile
+    static constexpr int R3 = (TH >> 3) * (TW >> 3), R4 = (TH >> 4) * (TW >> 4), R5 = (TH >> 5) * (TW >> 5);
+    static constexpr int QMAX = 3 * (R3 + R4 + R5) + R3;      // >= the count for any L <= 5
+    static constexpr int QPT = (QMAX + NT - 1) / NT;           // prefetched values per thread
     static_assert(RY == 4 && RX * SX::kBytes == 16, "register block is 4 rows x 16 bytes");
     static_assert(TH % 32 == 0 && TW % 32 == 0, "tile must hold whole 32x32 blocks");
 };
@@ -340,6 +344,46 @@ __device__ __forceinline__ void inv2d_tile(const Pass2D& p, int64_t item, int64_
         reinterpret_cast<typename SX::raw*>(p.dst) + item * p.dst_bstride + r0 * p.dst_pitch + c0;
     const int64_t dp = p.det_pitch, lp = p.ll_pitch;
 
+    // ---- small levels first: LL_L and the bands of levels 3..L, one flat
+    // index space (level by level: HL, LH, HH, then LL_L), loaded before the
+    // large level-1/2 loads so that they are the first to arrive
+    float pre[G::QPT];
+    int nq = 0;
+    if (L >= 3) {
+#pragma unroll
+        for (int u = 0; u < G::QPT; ++u) {
+            int q = t + u * NT;
+            pre[u] = 0.0f;
+            int off = 0;
+            for (int lev = 3; lev <= L + 1; ++lev) {
+                const int rows = TH >> (lev <= L ? lev : L), cols = TW >> (lev <= L ? lev : L);
+                const int cnt = lev <= L ? 3 * rows * cols : rows * cols;
+                if (q >= off && q < off + cnt) {
+                    const int e = q - off;
+                    const int band = lev <= L ? e / (rows * cols) : 3;   // 3 = LL_L
+                    const int ij = e - (lev <= L ? band : 0) * rows * cols;
+                    const int i = ij / cols, k = ij - i * cols;
+                    const int lv = lev <= L ? lev : L;
+                    const int oh = (int)ceil_shift(th, lv - 1), ow = (int)ceil_shift(tw, lv - 1);
+                    const int rh = (int)ceil_shift(th, lv), rw = (int)ceil_shift(tw, lv);
+                    const int64_t hs = ceil_shift(p.h, lv), ws = ceil_shift(p.w, lv);
+                    const int64_t R = (r0 >> lv) + i, C = (c0 >> lv) + k;
+                    if (band == 0) {          // HL: rows of LL_lv, odd column pairs
+                        if (i < rh && 2 * k + 1 < ow) pre[u] = ld1<SD>(det + R * dp + ws + C);
+                    } else if (band == 1) {   // LH
+                        if (2 * i + 1 < oh && k < rw) pre[u] = ld1<SD>(det + (hs + R) * dp + C);
+                    } else if (band == 2) {   // HH
+                        if (2 * i + 1 < oh && 2 * k + 1 < ow) pre[u] = ld1<SD>(det + (hs + R) * dp + ws + C);
+                    } else {                  // LL_L
+                        if (i < rh && k < rw) pre[u] = ld1<SL>(llp + R * lp + C);
+                    }
+                }
+                off += cnt;
+            }
+            nq = off;
+        }
+    }
+
     // ---- level-1 details of this thread's block
     float hl1[B1Y][B1X], lh1[B1Y][B1X], hh1[B1Y][B1X];
     {
@@ -389,29 +433,39 @@ __device__ __forceinline__ void inv2d_tile(const Pass2D& p, int64_t item, int64_
         }
     }
 
-    // ---- levels L..3 in LDS, producing the LL2 region in buffer A (pitch TW/4)
+    // ---- levels L..3 in LDS from the prefetched values, producing the LL2
+    // region in buffer A (pitch TW/4)
     float* A = sm;
     float* B = sm + G::AN;
+    float* D = sm + G::AN + G::BN;
     if (L >= 3) {
+#pragma unroll
+        for (int u = 0; u < G::QPT; ++u)
+            if (t + u * NT < nq) D[t + u * NT] = pre[u];
+        __syncthreads();
+        int off = 0;
+        int offs[6];
+        for (int lev = 3; lev <= L; ++lev) {
+            offs[lev] = off;
+            off += 3 * (TH >> lev) * (TW >> lev);
+        }
+        const float* Dll = D + off;
         for (int lev = L; lev >= 3; --lev) {
-            // LL_lev region (local) and the LL_{lev-1} region it expands into
+            const int rows = TH >> lev, cols = TW >> lev;
             const int rh = (int)ceil_shift(th, lev), rw = (int)ceil_shift(tw, lev);
             const int oh = (int)ceil_shift(th, lev - 1), ow = (int)ceil_shift(tw, lev - 1);
             const float* in = (lev & 1) ? B : A;     // output of level lev+1
             float* out = (lev & 1) ? A : B;
             const int pin = TW >> lev, pout = TW >> (lev - 1);
-            const int64_t hs = ceil_shift(p.h, lev), ws = ceil_shift(p.w, lev);
-            const int64_t R0 = r0 >> lev, C0 = c0 >> lev;
+            const float* Dh = D + offs[lev];
             for (int b = t; b < rh * rw; b += NT) {
                 const int i = b / rw, k = b - i * rw;
-                const int64_t R = R0 + i, C = C0 + k;
                 const bool r1 = 2 * i + 1 < oh, c1 = 2 * k + 1 < ow;
-                const float ll = (lev == L) ? ld1<SL>(llp + R * lp + C) : in[i * pin + k];
-                const float hl = c1 ? ld1<SD>(det + R * dp + ws + C) : 0.0f;
-                const float lh = r1 ? ld1<SD>(det + (hs + R) * dp + C) : 0.0f;
-                const float hh = (r1 && c1) ? ld1<SD>(det + (hs + R) * dp + ws + C) : 0.0f;
+                const int e = i * cols + k;
+                const float ll = (lev == L) ? Dll[e] : in[i * pin + k];
                 float x00, x01, x10, x11;
-                syn_edge(ll, hl, lh, hh, r1, c1, x00, x01, x10, x11);
+                syn_edge(ll, Dh[e], Dh[rows * cols + e], Dh[2 * rows * cols + e], r1, c1, x00, x01,
+                         x10, x11);
                 const int o = (2 * i) * pout + 2 * k;
                 out[o] = x00;
                 if (c1) out[o + 1] = x01;
@@ -489,66 +543,94 @@ __device__ __forceinline__ void inv2d_tile(const Pass2D& p, int64_t item, int64_
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX>
-__global__ __launch_bounds__(GY* GX) void fwd2d_kernel(Pass2D p) {
-    using G = Geo2D<SX, RY, RX, GY, GX>;
-    __shared__ float sm[G::SMEM];
-    const bool remap = (int64_t)gridDim.x == p.total_tiles;
-    for (int64_t b = blockIdx.x; b < p.total_tiles; b += gridDim.x) {
-        const int64_t tile = remap ? xcd_tile(b, p.total_tiles) : b;
-        const int64_t item = tile / p.tiles_per_item;
-        const int64_t rem = tile - item * p.tiles_per_item;
-        const int64_t ty = rem / p.tiles_x, tx = rem - ty * p.tiles_x;
-        const bool full = p.vec_ok && (ty + 1) * G::TH <= p.h && (tx + 1) * G::TW <= p.w;
-        if (full)
-            fwd2d_tile<SX, SD, SL, RY, RX, GY, GX, true>(p, item, ty, tx, sm);
-        else
-            fwd2d_tile<SX, SD, SL, RY, RX, GY, GX, false>(p, item, ty, tx, sm);
-        if (b + gridDim.x < p.total_tiles) __syncthreads();
+#ifndef HAAR_MIN_WAVES_2D
+#define HAAR_MIN_WAVES_2D 1
+#endif
+
+// Tile index -> (item, ty, tx).  Interior launches (EDGE = false) walk the
+// grid of full tiles and run the vector path only; edge launches walk the
+// right column and bottom row of partial tiles, or every tile when the
+// layout is not aligned for vectors (p.vec_ok == 0), on the scalar path.
+template <bool EDGE>
+__device__ __forceinline__ void tile_coords(const Pass2D& p, int64_t tile, int64_t& item,
+                                            int64_t& ty, int64_t& tx) {
+    if (!EDGE) {
+        const int64_t per = p.full_x * p.full_y;
+        item = tile / per;
+        const int64_t r = tile - item * per;
+        ty = r / p.full_x;
+        tx = r - ty * p.full_x;
+    } else if (!p.vec_ok) {
+        item = tile / p.tiles_per_item;
+        const int64_t r = tile - item * p.tiles_per_item;
+        ty = r / p.tiles_x;
+        tx = r - ty * p.tiles_x;
+    } else {
+        const int64_t right = p.tiles_x > p.full_x ? p.full_y : 0;   // right column, full rows
+        const int64_t bottom = p.tiles_y > p.full_y ? p.tiles_x : 0;  // bottom row, all columns
+        const int64_t per = right + bottom;
+        item = tile / per;
+        const int64_t r = tile - item * per;
+        if (r < right) {
+            ty = r;
+            tx = p.full_x;
+        } else {
+            ty = p.full_y;
+            tx = r - right;
+        }
     }
 }
 
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX>
-__global__ __launch_bounds__(GY* GX) void inv2d_kernel(Pass2D p) {
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE>
+__global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D p, int64_t ntiles) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
-    __shared__ float sm[G::AN + G::BN];
-    const bool remap = (int64_t)gridDim.x == p.total_tiles;
-    for (int64_t b = blockIdx.x; b < p.total_tiles; b += gridDim.x) {
-        const int64_t tile = remap ? xcd_tile(b, p.total_tiles) : b;
-        const int64_t item = tile / p.tiles_per_item;
-        const int64_t rem = tile - item * p.tiles_per_item;
-        const int64_t ty = rem / p.tiles_x, tx = rem - ty * p.tiles_x;
-        const bool full = p.vec_ok && (ty + 1) * G::TH <= p.h && (tx + 1) * G::TW <= p.w;
-        if (full)
-            inv2d_tile<SX, SD, SL, RY, RX, GY, GX, true>(p, item, ty, tx, sm);
-        else
-            inv2d_tile<SX, SD, SL, RY, RX, GY, GX, false>(p, item, ty, tx, sm);
-        if (b + gridDim.x < p.total_tiles) __syncthreads();
+    __shared__ float sm[G::SMEM];
+    const bool remap = p.remap && (int64_t)gridDim.x == ntiles;
+    for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        int64_t item, ty, tx;
+        tile_coords<EDGE>(p, remap ? xcd_tile(b, ntiles) : b, item, ty, tx);
+        fwd2d_tile<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, sm);
+        if (b + gridDim.x < ntiles) __syncthreads();
+    }
+}
+
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE>
+__global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D p, int64_t ntiles) {
+    using G = Geo2D<SX, RY, RX, GY, GX>;
+    __shared__ float sm[G::AN + G::BN + G::QPT * G::NT];
+    const bool remap = p.remap && (int64_t)gridDim.x == ntiles;
+    for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        int64_t item, ty, tx;
+        tile_coords<EDGE>(p, remap ? xcd_tile(b, ntiles) : b, item, ty, tx);
+        inv2d_tile<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, sm);
+        if (b + gridDim.x < ntiles) __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // Tile-shape table and launchers
 // ---------------------------------------------------------------------------
-// Index -> (GY, GX); RY = 4 and RX = 16 bytes / element size.
+// Index -> (GY, GX, XCD remap); RY = 4 and RX = 16 bytes / element size.
 #define HAAR_2D_TILES(X) \
-    X(0, 8, 32)          \
-    X(1, 8, 16)          \
-    X(2, 16, 16)         \
-    X(3, 8, 64)
+    X(0, 8, 32, 1)       \
+    X(1, 8, 32, 0)       \
+    X(2, 8, 64, 1)       \
+    X(3, 8, 64, 0)       \
+    X(4, 8, 16, 1)       \
+    X(5, 16, 16, 1)
 
-int num_tile_configs_2d(int) { return 4; }
+int num_tile_configs_2d(int) { return 6; }
 
 Tile2D tile_config_2d(int elem_bytes, int index) {
     const int rx = 16 / elem_bytes;
     switch (index) {
-#define X(I, GY_, GX_) \
-    case I:            \
-        return Tile2D{4, rx, GY_, GX_};
+#define X(I, GY_, GX_, RM_) \
+    case I:                 \
+        return Tile2D{4, rx, GY_, GX_, RM_};
         HAAR_2D_TILES(X)
 #undef X
         default:
-            return Tile2D{4, rx, 8, 32};
+            return Tile2D{4, rx, 8, 32, 1};
     }
 }
 
@@ -556,19 +638,37 @@ template <class SX, class SD, class SL, int GY, int GX>
 static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     constexpr int RX = 16 / SX::kBytes;
     constexpr int64_t kMaxGrid = 1 << 20;
-    const unsigned grid = (unsigned)(p.total_tiles < kMaxGrid ? p.total_tiles : kMaxGrid);
-    if (inverse)
-        hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX>), dim3(grid), dim3(GY * GX), 0, s, p);
-    else
-        hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX>), dim3(grid), dim3(GY * GX), 0, s, p);
-    return hipGetLastError();
+    const int64_t interior = p.vec_ok ? p.full_x * p.full_y * p.batch : 0;
+    const int64_t edge = p.total_tiles - interior;
+    if (interior > 0) {
+        const unsigned grid = (unsigned)(interior < kMaxGrid ? interior : kMaxGrid);
+        if (inverse)
+            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, false>), dim3(grid),
+                               dim3(GY * GX), 0, s, p, interior);
+        else
+            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, false>), dim3(grid),
+                               dim3(GY * GX), 0, s, p, interior);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (edge > 0) {
+        const unsigned grid = (unsigned)(edge < kMaxGrid ? edge : kMaxGrid);
+        if (inverse)
+            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, true>), dim3(grid),
+                               dim3(GY * GX), 0, s, p, edge);
+        else
+            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, true>), dim3(grid),
+                               dim3(GY * GX), 0, s, p, edge);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 template <class S>
 static hipError_t dispatch2d(const Pass2D& p, int cfg, bool inverse, hipStream_t s) {
     switch (cfg) {
-#define X(I, GY_, GX_) \
-    case I:            \
+#define X(I, GY_, GX_, RM_) \
+    case I:                 \
         return launch2d<S, S, S, GY_, GX_>(p, inverse, s);
         HAAR_2D_TILES(X)
 #undef X

@@ -96,8 +96,10 @@ static std::vector<Region2D> passes_2d(int64_t h, int64_t w, int L) {
 
 static void tile_grid(Pass2D& p, const Tile2D& tc) {
     p.tiles_x = (p.w + tc.tw() - 1) / tc.tw();
-    const int64_t ty = (p.h + tc.th() - 1) / tc.th();
-    p.tiles_per_item = ty * p.tiles_x;
+    p.tiles_y = (p.h + tc.th() - 1) / tc.th();
+    p.full_x = p.w / tc.tw();
+    p.full_y = p.h / tc.th();
+    p.tiles_per_item = p.tiles_y * p.tiles_x;
     p.total_tiles = p.tiles_per_item * p.batch;
 }
 
@@ -167,7 +169,9 @@ int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch
             p.dst = rptr; p.dst_pitch = rpitch; p.dst_bstride = rbs;
         }
         p.ll = lptr; p.ll_pitch = lpitch; p.ll_bstride = lbs;
-        tile_grid(p, tile_config_2d(ebx, pcfg));
+        const Tile2D tc = tile_config_2d(ebx, pcfg);
+        tile_grid(p, tc);
+        p.remap = tc.remap;
         p.vec_ok = vec_ok_2d(p, inverse, ebx, ebl);
         hipError_t e = inverse ? launch_inv2d(p, dtype, pcfg, x_f32, ll_f32, s)
                                : launch_fwd2d(p, dtype, pcfg, x_f32, ll_f32, s);
@@ -257,6 +261,7 @@ int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype
         else { p.dst = rptr; p.dst_bstride = rbs; }
         p.ll = k == np - 1 ? (void*)(inverse ? in : out) : (void*)buf(k + 1);
         p.ll_bstride = k == np - 1 ? N : nn;
+        p.remap = cc.remap;
         p.chunks_per_item = (r.n + cc.chunk() - 1) / cc.chunk();
         p.total_chunks = p.chunks_per_item * batch;
         p.vec_ok = vec_ok_1d(p, inverse, ebx, eb, cc);

@@ -139,6 +139,33 @@ struct StF16 {
     }
 };
 
+// Outputs are written with nontemporal (streaming) stores: every output
+// element is written once and not read again by the kernel, and streaming
+// stores avoid allocating the lines in the caches on the way to HBM.
+// Inputs use ordinary loads unless HAAR_NT_LOADS is set.
+#ifndef HAAR_NT_LOADS
+#define HAAR_NT_LOADS 0
+#endif
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ __forceinline__ T ld_any(const T* p) {
+#if HAAR_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <class T>
+__device__ __forceinline__ void st_any(T v, T* p) {
+    __builtin_nontemporal_store(v, p);
+}
+
 // Load N consecutive elements (N * kBytes in {2, 4, 8, 16}, pointer aligned
 // to that size) into floats.
 template <class S, int N>
@@ -147,26 +174,26 @@ __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
     static_assert(B == 2 || B == 4 || B == 8 || B == 16, "vector width");
     if constexpr (S::kBytes == 4) {
         if constexpr (N == 4) {
-            const float4 v = *reinterpret_cast<const float4*>(p);
+            const v4f v = ld_any(reinterpret_cast<const v4f*>(p));
             out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
         } else if constexpr (N == 2) {
-            const float2 v = *reinterpret_cast<const float2*>(p);
+            const v2f v = ld_any(reinterpret_cast<const v2f*>(p));
             out[0] = v.x; out[1] = v.y;
         } else {
-            out[0] = p[0];
+            out[0] = ld_any(reinterpret_cast<const float*>(p));
         }
     } else {
         uint32_t w[B >= 4 ? B / 4 : 1];
         if constexpr (B == 16) {
-            const uint4 v = *reinterpret_cast<const uint4*>(p);
+            const v4u v = ld_any(reinterpret_cast<const v4u*>(p));
             w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
         } else if constexpr (B == 8) {
-            const uint2 v = *reinterpret_cast<const uint2*>(p);
+            const v2u v = ld_any(reinterpret_cast<const v2u*>(p));
             w[0] = v.x; w[1] = v.y;
         } else if constexpr (B == 4) {
-            w[0] = *reinterpret_cast<const uint32_t*>(p);
+            w[0] = ld_any(reinterpret_cast<const uint32_t*>(p));
         } else {
-            out[0] = S::ld(p[0]);
+            out[0] = S::ld(ld_any(p));
             return;
         }
 #pragma unroll
@@ -183,36 +210,40 @@ __device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {
     static_assert(B == 2 || B == 4 || B == 8 || B == 16, "vector width");
     if constexpr (S::kBytes == 4) {
         if constexpr (N == 4) {
-            *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+            v4f o = {v[0], v[1], v[2], v[3]};
+            st_any(o, reinterpret_cast<v4f*>(p));
         } else if constexpr (N == 2) {
-            *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+            v2f o = {v[0], v[1]};
+            st_any(o, reinterpret_cast<v2f*>(p));
         } else {
-            p[0] = v[0];
+            st_any(v[0], reinterpret_cast<float*>(p));
         }
     } else {
         if constexpr (B == 2) {
-            p[0] = S::st(v[0]);
+            st_any(S::st(v[0]), p);
         } else {
             uint32_t w[B / 4];
 #pragma unroll
             for (int i = 0; i < N / 2; ++i)
                 w[i] = (uint32_t)S::st(v[2 * i]) | ((uint32_t)S::st(v[2 * i + 1]) << 16);
             if constexpr (B == 16) {
-                *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+                v4u o = {w[0], w[1], w[2], w[3]};
+                st_any(o, reinterpret_cast<v4u*>(p));
             } else if constexpr (B == 8) {
-                *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+                v2u o = {w[0], w[1]};
+                st_any(o, reinterpret_cast<v2u*>(p));
             } else {
-                *reinterpret_cast<uint32_t*>(p) = w[0];
+                st_any(w[0], reinterpret_cast<uint32_t*>(p));
             }
         }
     }
 }
 
 template <class S>
-__device__ __forceinline__ void st1(typename S::raw* p, float v) { *p = S::st(v); }
+__device__ __forceinline__ void st1(typename S::raw* p, float v) { st_any(S::st(v), p); }
 
 template <class S>
-__device__ __forceinline__ float ld1(const typename S::raw* p) { return S::ld(*p); }
+__device__ __forceinline__ float ld1(const typename S::raw* p) { return S::ld(ld_any(p)); }
 
 // ceil(n / 2^j)
 __device__ __forceinline__ int64_t ceil_shift(int64_t n, int j) {
@@ -220,7 +251,9 @@ __device__ __forceinline__ int64_t ceil_shift(int64_t n, int j) {
 }
 
 // Map a block index to a tile index so that the tiles handled by one XCD
-// (blocks are dealt round-robin to the 8 XCDs) form one contiguous range.
+// (blocks are dealt round-robin to the 8 XCDs) form one contiguous range:
+// neighbouring tiles then share that XCD's L2 for the partial cache lines of
+// their small deep-level band segments.
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
     const int64_t q = total >> 3, r = total & 7;
     const int64_t x = b & 7, i = b >> 3;

@@ -18,7 +18,9 @@ struct Pass2D {
     int64_t h, w, batch;
     int32_t levels;
     int32_t vec_ok;                         // launch-wide: bases/pitches/band origins aligned
-    int64_t tiles_x, tiles_per_item, total_tiles;
+    int64_t tiles_x, tiles_y, tiles_per_item, total_tiles;
+    int64_t full_x, full_y;                 // tiles that lie entirely inside the region
+    int32_t remap;                          // deal contiguous tile ranges to each XCD
 };
 
 // One fused 1D pass: `levels` levels on a length-n region (chunks of C).
@@ -31,12 +33,14 @@ struct Pass1D {
     int32_t levels;
     int32_t vec_ok;
     int64_t chunks_per_item, total_chunks;
+    int32_t remap;                          // deal contiguous chunk ranges to each XCD
 };
 
 // Tile shapes of the 2D kernels (per storage width): rows/cols per thread
 // and the thread grid of one work-group.
 struct Tile2D {
     int ry, rx, gy, gx;
+    int remap;
     int th() const { return gy * ry; }
     int tw() const { return gx * rx; }
     int threads() const { return gy * gx; }
@@ -57,6 +61,7 @@ hipError_t launch_inv2d(const Pass2D& p, int dtype, int cfg, bool x_f32, bool ll
 // 1D chunk kernels: chunk = threads * elems_per_thread; on-chip depth log2(chunk).
 struct Chunk1D {
     int threads, ept;
+    int remap;
     int chunk() const { return threads * ept; }
 };
 int num_chunk_configs_1d();
