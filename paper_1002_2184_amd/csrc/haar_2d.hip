@@ -108,9 +108,41 @@ struct Geo2D {
     static_assert(TH % 32 == 0 && TW % 32 == 0, "tile must hold whole 32x32 blocks");
 };
 
+// Register block of one analysis tile: the RY x RX input samples of a thread.
+template <int RY, int RX>
+struct FwdIn {
+    float v[RY][RX];
+};
+
+template <class SX, int RY, int RX, int GY, int GX, bool FULL>
+__device__ __forceinline__ void fwd2d_load(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
+                                           FwdIn<RY, RX>& in) {
+    using G = Geo2D<SX, RY, RX, GY, GX>;
+    constexpr int TH = G::TH, TW = G::TW;
+    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
+    const int64_t r0 = ty * TH, c0 = tx * TW;
+    const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
+    const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
+    const int lr0 = rg * RY, lc0 = cg * RX;
+    const typename SX::raw* src =
+        reinterpret_cast<const typename SX::raw*>(p.src) + item * p.src_bstride + r0 * p.src_pitch + c0;
+    if constexpr (FULL) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) ld_vec<SX, RX>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0, in.v[r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int c = 0; c < RX; ++c)
+                in.v[r][c] = (lr0 + r < th && lc0 + c < tw)
+                                 ? ld1<SX>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0 + c)
+                                 : 0.0f;
+    }
+}
+
 template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
-__device__ __forceinline__ void fwd2d_tile(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
-                                           float* sm) {
+__device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
+                                           const FwdIn<RY, RX>& in, float* sm) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
     constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
     constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
@@ -122,26 +154,10 @@ __device__ __forceinline__ void fwd2d_tile(const Pass2D& p, int64_t item, int64_
     const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
     const int lr0 = rg * RY, lc0 = cg * RX;            // local origin of this thread's block
 
-    const typename SX::raw* src =
-        reinterpret_cast<const typename SX::raw*>(p.src) + item * p.src_bstride + r0 * p.src_pitch + c0;
     typename SD::raw* det = reinterpret_cast<typename SD::raw*>(p.det) + item * p.det_bstride;
     typename SL::raw* llp = reinterpret_cast<typename SL::raw*>(p.ll) + item * p.ll_bstride;
     const int64_t dp = p.det_pitch, lp = p.ll_pitch;
-
-    // ---- load the register block
-    float v[RY][RX];
-    if constexpr (FULL) {
-#pragma unroll
-        for (int r = 0; r < RY; ++r) ld_vec<SX, RX>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0, v[r]);
-    } else {
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int c = 0; c < RX; ++c)
-                v[r][c] = (lr0 + r < th && lc0 + c < tw)
-                              ? ld1<SX>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0 + c)
-                              : 0.0f;
-    }
+    const auto& v = in.v;
 
     // ---- level 1 (registers)
     df a1[B1Y][B1X];
@@ -265,23 +281,70 @@ __device__ __forceinline__ void fwd2d_tile(const Pass2D& p, int64_t item, int64_
         }
     }
 
-    // ---- levels 3..L (LDS); buffer A holds LL2 (pitch TW/4)
+    // ---- levels 3..L.  Buffer A holds LL2 (pitch TW/4), buffer B LL3 (pitch TW/8).
     float* Ahi = sm;
     float* Alo = sm + G::AN;
     float* Bhi = sm + 2 * G::AN;
     float* Blo = Bhi + G::BN;
-#pragma unroll
-    for (int i = 0; i < B2Y; ++i)
-#pragma unroll
-        for (int k = 0; k < B2X; ++k) {
-            const int idx = ((lr0 >> 2) + i) * (TW / 4) + (lc0 >> 2) + k;
-            Ahi[idx] = a2[i][k].hi;
-            Alo[idx] = a2[i][k].lo;
+    int rh = (th + 3) >> 2, rw = (tw + 3) >> 2;   // local region size at level 2
+    int first = 3;                                // first level of the single-wave phase
+    if constexpr (FULL && GX == 32) {
+        // Level 3 inside each wavefront: with 32 column groups a wave holds
+        // LL2 rows 2w (lanes 0-31) and 2w+1 (lanes 32-63), so every 2x2 block
+        // of LL2 lies in one wave: xor-shuffles fetch the partners.
+        const int lane = t & 63, w = t >> 6;
+        df x00, x01, x10, x11;
+        if constexpr (B2X == 1) {
+            const df a = a2[0][0];
+            x00 = a;
+            x01 = df{__shfl_xor(a.hi, 1), __shfl_xor(a.lo, 1)};
+            x10 = df{__shfl_xor(a.hi, 32), __shfl_xor(a.lo, 32)};
+            x11 = df{__shfl_xor(a.hi, 33), __shfl_xor(a.lo, 33)};
+        } else {
+            x00 = a2[0][0];
+            x01 = a2[0][1];
+            x10 = df{__shfl_xor(a2[0][0].hi, 32), __shfl_xor(a2[0][0].lo, 32)};
+            x11 = df{__shfl_xor(a2[0][1].hi, 32), __shfl_xor(a2[0][1].lo, 32)};
         }
+        const bool active = B2X == 1 ? (lane & 33) == 0 : lane < 32;
+        if (active) {
+            const int k = B2X == 1 ? (lane >> 1) : lane;     // level-3 column in the tile
+            df ll;
+            float hl, lh, hh;
+            ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
+            const int64_t hs = ceil_shift(p.h, 3), ws = ceil_shift(p.w, 3);
+            const int64_t R = (r0 >> 3) + w, C = (c0 >> 3) + k;
+            st1<SD>(det + R * dp + ws + C, hl);
+            st1<SD>(det + (hs + R) * dp + C, lh);
+            st1<SD>(det + (hs + R) * dp + ws + C, hh);
+            if (L == 3) {
+                st1<SL>(llp + R * lp + C, df_round(ll));
+            } else {
+                Bhi[w * (TW / 8) + k] = ll.hi;
+                Blo[w * (TW / 8) + k] = ll.lo;
+            }
+        }
+        if (L == 3) return;
+        rh = TH / 8;
+        rw = TW / 8;
+        first = 4;
+    } else {
+#pragma unroll
+        for (int i = 0; i < B2Y; ++i)
+#pragma unroll
+            for (int k = 0; k < B2X; ++k) {
+                const int idx = ((lr0 >> 2) + i) * (TW / 4) + (lc0 >> 2) + k;
+                Ahi[idx] = a2[i][k].hi;
+                Alo[idx] = a2[i][k].lo;
+            }
+    }
     __syncthreads();
 
-    int rh = (th + 3) >> 2, rw = (tw + 3) >> 2;   // local region size at level 2
-    for (int lev = 3; lev <= L; ++lev) {
+    // The remaining levels are small (at most (TH/8) x (TW/8) blocks): the
+    // first wavefront does them alone, ordered by wavefront-level barriers, so
+    // the other wavefronts of the work-group can retire.
+    if (t >= 64) return;
+    for (int lev = first; lev <= L; ++lev) {
         const bool odd = lev & 1;
         const float* ihi = odd ? Ahi : Bhi;
         const float* ilo = odd ? Alo : Blo;
@@ -291,7 +354,7 @@ __device__ __forceinline__ void fwd2d_tile(const Pass2D& p, int64_t item, int64_
         const int bh = (rh + 1) >> 1, bw = (rw + 1) >> 1;
         const int64_t hs = ceil_shift(p.h, lev), ws = ceil_shift(p.w, lev);
         const int64_t R0 = r0 >> lev, C0 = c0 >> lev;
-        for (int b = t; b < bh * bw; b += NT) {
+        for (int b = t; b < bh * bw; b += 64) {
             const int i = b / bw, k = b - i * bw;
             const bool r1 = 2 * i + 1 < rh, c1 = 2 * k + 1 < rw;
             const int i0 = (2 * i) * pin + 2 * k;
@@ -315,16 +378,162 @@ __device__ __forceinline__ void fwd2d_tile(const Pass2D& p, int64_t item, int64_
         }
         rh = bh;
         rw = bw;
-        if (lev < L) __syncthreads();
+        if (lev < L) {   // LDS written by some lanes, read by others of this wavefront
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Synthesis tile
 // ---------------------------------------------------------------------------
+// Everything one thread of a synthesis tile reads from HBM: its share of the
+// small levels (LL_L and the bands of levels 3..L, one flat index space:
+// level by level HL, LH, HH, then LL_L) and the level-1/2 details of its
+// register block.
+template <int QPT, int B1Y, int B1X, int B2Y, int B2X>
+struct InvIn {
+    float pre[QPT];      // edge tiles: share of the small levels, staged through LDS
+    float walk[10];      // interior tiles: LL_L, then (HL, LH, HH) of levels 3, 4, 5 on the
+                         // ancestor path of this thread's LL3 coefficient
+    float hl1[B1Y][B1X], lh1[B1Y][B1X], hh1[B1Y][B1X];
+    float hl2[B2Y][B2X], lh2[B2Y][B2X], hh2[B2Y][B2X];
+};
+
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX>
+using InvInT = InvIn<Geo2D<SX, RY, RX, GY, GX>::QPT, RY / 2, RX / 2, RY / 4, RX / 4>;
+
+// number of prefetched small-level values of a tile of L levels (L >= 3)
+template <int TH, int TW>
+__device__ __forceinline__ int small_count(int L) {
+    int off = 0;
+    for (int lev = 3; lev <= L; ++lev) off += 3 * (TH >> lev) * (TW >> lev);
+    return off + (TH >> L) * (TW >> L);
+}
+
 template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
-__device__ __forceinline__ void inv2d_tile(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
-                                           float* sm) {
+__device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
+                                           InvInT<SX, SD, SL, RY, RX, GY, GX>& in) {
+    using G = Geo2D<SX, RY, RX, GY, GX>;
+    constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
+    constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
+    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
+    const int64_t r0 = ty * TH, c0 = tx * TW;
+    const int L = p.levels;
+    const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
+    const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
+    const int lr0 = rg * RY, lc0 = cg * RX;
+    const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
+    const typename SD::raw* det = reinterpret_cast<const typename SD::raw*>(p.det) + item * p.det_bstride;
+    const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
+    const int64_t dp = p.det_pitch, lp = p.ll_pitch;
+
+    // ---- interior tiles: the ancestor path of this thread's LL3 coefficient,
+    // LL_L then (HL, LH, HH) of levels L..3, loaded first (many lanes share
+    // these addresses, so most requests hit in cache)
+    if (FULL && L >= 3) {
+        const int64_t R3 = ((r0 >> 2) + (lr0 >> 2)) >> 1, C3 = ((c0 >> 2) + (lc0 >> 2)) >> 1;
+        in.walk[0] = ld1<SL>(llp + (R3 >> (L - 3)) * lp + (C3 >> (L - 3)));
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            const int j = 3 + jj;
+            if (j <= L) {
+                const int64_t hs = ceil_shift(p.h, j), ws = ceil_shift(p.w, j);
+                const int64_t R = R3 >> (j - 3), C = C3 >> (j - 3);
+                in.walk[1 + 3 * jj] = ld1<SD>(det + R * dp + ws + C);
+                in.walk[2 + 3 * jj] = ld1<SD>(det + (hs + R) * dp + C);
+                in.walk[3 + 3 * jj] = ld1<SD>(det + (hs + R) * dp + ws + C);
+            }
+        }
+    }
+    // ---- edge tiles: small levels first, so that they are the first to arrive
+    if (!FULL && L >= 3) {
+#pragma unroll
+        for (int u = 0; u < G::QPT; ++u) {
+            const int q = t + u * NT;
+            in.pre[u] = 0.0f;
+            int off = 0;
+            for (int lev = 3; lev <= L + 1; ++lev) {
+                const int lv = lev <= L ? lev : L;
+                const int rows = TH >> lv, cols = TW >> lv;
+                const int cnt = lev <= L ? 3 * rows * cols : rows * cols;
+                if (q >= off && q < off + cnt) {
+                    const int e = q - off;
+                    const int band = lev <= L ? e / (rows * cols) : 3;   // 3 = LL_L
+                    const int ij = e - (lev <= L ? band : 0) * rows * cols;
+                    const int i = ij / cols, k = ij - i * cols;
+                    const int oh = (int)ceil_shift(th, lv - 1), ow = (int)ceil_shift(tw, lv - 1);
+                    const int rh = (int)ceil_shift(th, lv), rw = (int)ceil_shift(tw, lv);
+                    const int64_t hs = ceil_shift(p.h, lv), ws = ceil_shift(p.w, lv);
+                    const int64_t R = (r0 >> lv) + i, C = (c0 >> lv) + k;
+                    if (band == 0) {          // HL: rows of LL_lv, odd column pairs
+                        if (i < rh && 2 * k + 1 < ow) in.pre[u] = ld1<SD>(det + R * dp + ws + C);
+                    } else if (band == 1) {   // LH
+                        if (2 * i + 1 < oh && k < rw) in.pre[u] = ld1<SD>(det + (hs + R) * dp + C);
+                    } else if (band == 2) {   // HH
+                        if (2 * i + 1 < oh && 2 * k + 1 < ow)
+                            in.pre[u] = ld1<SD>(det + (hs + R) * dp + ws + C);
+                    } else {                  // LL_L
+                        if (i < rh && k < rw) in.pre[u] = ld1<SL>(llp + R * lp + C);
+                    }
+                }
+                off += cnt;
+            }
+        }
+    }
+    // ---- level-1 details of this thread's block
+    {
+        const int64_t hs = ceil_shift(p.h, 1), ws = ceil_shift(p.w, 1);
+        const int64_t R = (r0 >> 1) + (lr0 >> 1), C = (c0 >> 1) + (lc0 >> 1);
+#pragma unroll
+        for (int i = 0; i < B1Y; ++i) {
+            if constexpr (FULL) {
+                ld_vec<SD, B1X>(det + (R + i) * dp + ws + C, in.hl1[i]);
+                ld_vec<SD, B1X>(det + (hs + R + i) * dp + C, in.lh1[i]);
+                ld_vec<SD, B1X>(det + (hs + R + i) * dp + ws + C, in.hh1[i]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < B1X; ++k) {
+                    const int lr = lr0 + 2 * i, lc = lc0 + 2 * k;
+                    const bool ok = lr < th && lc < tw;
+                    const bool r1 = ok && lr + 1 < th, c1 = ok && lc + 1 < tw;
+                    in.hl1[i][k] = c1 ? ld1<SD>(det + (R + i) * dp + ws + C + k) : 0.0f;
+                    in.lh1[i][k] = r1 ? ld1<SD>(det + (hs + R + i) * dp + C + k) : 0.0f;
+                    in.hh1[i][k] = (r1 && c1) ? ld1<SD>(det + (hs + R + i) * dp + ws + C + k) : 0.0f;
+                }
+            }
+        }
+    }
+    // ---- level-2 details (LL1 itself when L == 1, read into hl2's place: see body)
+    if (L >= 2) {
+        const int64_t hs = ceil_shift(p.h, 2), ws = ceil_shift(p.w, 2);
+        const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
+#pragma unroll
+        for (int i = 0; i < B2Y; ++i) {
+            if constexpr (FULL) {
+                ld_vec<SD, B2X>(det + (R + i) * dp + ws + C, in.hl2[i]);
+                ld_vec<SD, B2X>(det + (hs + R + i) * dp + C, in.lh2[i]);
+                ld_vec<SD, B2X>(det + (hs + R + i) * dp + ws + C, in.hh2[i]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < B2X; ++k) {
+                    const int lr = (lr0 >> 1) + 2 * i, lc = (lc0 >> 1) + 2 * k;
+                    const bool ok = lr < th1 && lc < tw1;
+                    const bool r1 = ok && lr + 1 < th1, c1 = ok && lc + 1 < tw1;
+                    in.hl2[i][k] = c1 ? ld1<SD>(det + (R + i) * dp + ws + C + k) : 0.0f;
+                    in.lh2[i][k] = r1 ? ld1<SD>(det + (hs + R + i) * dp + C + k) : 0.0f;
+                    in.hh2[i][k] = (r1 && c1) ? ld1<SD>(det + (hs + R + i) * dp + ws + C + k) : 0.0f;
+                }
+            }
+        }
+    }
+}
+
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
+__device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
+                                           const InvInT<SX, SD, SL, RY, RX, GY, GX>& in, float* sm) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
     constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
     constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
@@ -338,107 +547,25 @@ __device__ __forceinline__ void inv2d_tile(const Pass2D& p, int64_t item, int64_
     const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
     const int th2 = (th + 3) >> 2, tw2 = (tw + 3) >> 2;
 
-    const typename SD::raw* det = reinterpret_cast<const typename SD::raw*>(p.det) + item * p.det_bstride;
     const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
     typename SX::raw* dst =
         reinterpret_cast<typename SX::raw*>(p.dst) + item * p.dst_bstride + r0 * p.dst_pitch + c0;
-    const int64_t dp = p.det_pitch, lp = p.ll_pitch;
-
-    // ---- small levels first: LL_L and the bands of levels 3..L, one flat
-    // index space (level by level: HL, LH, HH, then LL_L), loaded before the
-    // large level-1/2 loads so that they are the first to arrive
-    float pre[G::QPT];
-    int nq = 0;
-    if (L >= 3) {
-#pragma unroll
-        for (int u = 0; u < G::QPT; ++u) {
-            int q = t + u * NT;
-            pre[u] = 0.0f;
-            int off = 0;
-            for (int lev = 3; lev <= L + 1; ++lev) {
-                const int rows = TH >> (lev <= L ? lev : L), cols = TW >> (lev <= L ? lev : L);
-                const int cnt = lev <= L ? 3 * rows * cols : rows * cols;
-                if (q >= off && q < off + cnt) {
-                    const int e = q - off;
-                    const int band = lev <= L ? e / (rows * cols) : 3;   // 3 = LL_L
-                    const int ij = e - (lev <= L ? band : 0) * rows * cols;
-                    const int i = ij / cols, k = ij - i * cols;
-                    const int lv = lev <= L ? lev : L;
-                    const int oh = (int)ceil_shift(th, lv - 1), ow = (int)ceil_shift(tw, lv - 1);
-                    const int rh = (int)ceil_shift(th, lv), rw = (int)ceil_shift(tw, lv);
-                    const int64_t hs = ceil_shift(p.h, lv), ws = ceil_shift(p.w, lv);
-                    const int64_t R = (r0 >> lv) + i, C = (c0 >> lv) + k;
-                    if (band == 0) {          // HL: rows of LL_lv, odd column pairs
-                        if (i < rh && 2 * k + 1 < ow) pre[u] = ld1<SD>(det + R * dp + ws + C);
-                    } else if (band == 1) {   // LH
-                        if (2 * i + 1 < oh && k < rw) pre[u] = ld1<SD>(det + (hs + R) * dp + C);
-                    } else if (band == 2) {   // HH
-                        if (2 * i + 1 < oh && 2 * k + 1 < ow) pre[u] = ld1<SD>(det + (hs + R) * dp + ws + C);
-                    } else {                  // LL_L
-                        if (i < rh && k < rw) pre[u] = ld1<SL>(llp + R * lp + C);
-                    }
-                }
-                off += cnt;
-            }
-            nq = off;
-        }
-    }
-
-    // ---- level-1 details of this thread's block
-    float hl1[B1Y][B1X], lh1[B1Y][B1X], hh1[B1Y][B1X];
-    {
-        const int64_t hs = ceil_shift(p.h, 1), ws = ceil_shift(p.w, 1);
-        const int64_t R = (r0 >> 1) + (lr0 >> 1), C = (c0 >> 1) + (lc0 >> 1);
-#pragma unroll
-        for (int i = 0; i < B1Y; ++i) {
-            if constexpr (FULL) {
-                ld_vec<SD, B1X>(det + (R + i) * dp + ws + C, hl1[i]);
-                ld_vec<SD, B1X>(det + (hs + R + i) * dp + C, lh1[i]);
-                ld_vec<SD, B1X>(det + (hs + R + i) * dp + ws + C, hh1[i]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < B1X; ++k) {
-                    const int lr = lr0 + 2 * i, lc = lc0 + 2 * k;
-                    const bool ok = lr < th && lc < tw;
-                    const bool r1 = ok && lr + 1 < th, c1 = ok && lc + 1 < tw;
-                    hl1[i][k] = c1 ? ld1<SD>(det + (R + i) * dp + ws + C + k) : 0.0f;
-                    lh1[i][k] = r1 ? ld1<SD>(det + (hs + R + i) * dp + C + k) : 0.0f;
-                    hh1[i][k] = (r1 && c1) ? ld1<SD>(det + (hs + R + i) * dp + ws + C + k) : 0.0f;
-                }
-            }
-        }
-    }
-    // ---- level-2 details
-    float hl2[B2Y][B2X], lh2[B2Y][B2X], hh2[B2Y][B2X];
-    if (L >= 2) {
-        const int64_t hs = ceil_shift(p.h, 2), ws = ceil_shift(p.w, 2);
-        const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
-#pragma unroll
-        for (int i = 0; i < B2Y; ++i) {
-            if constexpr (FULL) {
-                ld_vec<SD, B2X>(det + (R + i) * dp + ws + C, hl2[i]);
-                ld_vec<SD, B2X>(det + (hs + R + i) * dp + C, lh2[i]);
-                ld_vec<SD, B2X>(det + (hs + R + i) * dp + ws + C, hh2[i]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < B2X; ++k) {
-                    const int lr = (lr0 >> 1) + 2 * i, lc = (lc0 >> 1) + 2 * k;
-                    const bool ok = lr < th1 && lc < tw1;
-                    const bool r1 = ok && lr + 1 < th1, c1 = ok && lc + 1 < tw1;
-                    hl2[i][k] = c1 ? ld1<SD>(det + (R + i) * dp + ws + C + k) : 0.0f;
-                    lh2[i][k] = r1 ? ld1<SD>(det + (hs + R + i) * dp + C + k) : 0.0f;
-                    hh2[i][k] = (r1 && c1) ? ld1<SD>(det + (hs + R + i) * dp + ws + C + k) : 0.0f;
-                }
-            }
-        }
-    }
+    const int64_t lp = p.ll_pitch;
+    const auto& hl1 = in.hl1;
+    const auto& lh1 = in.lh1;
+    const auto& hh1 = in.hh1;
+    const auto& hl2 = in.hl2;
+    const auto& lh2 = in.lh2;
+    const auto& hh2 = in.hh2;
+    const int nq = L >= 3 ? small_count<TH, TW>(L) : 0;
+    const auto& pre = in.pre;
 
     // ---- levels L..3 in LDS from the prefetched values, producing the LL2
-    // region in buffer A (pitch TW/4)
+    // region in buffer A (pitch TW/4) (edge tiles)
     float* A = sm;
     float* B = sm + G::AN;
     float* D = sm + G::AN + G::BN;
-    if (L >= 3) {
+    if (!FULL && L >= 3) {
 #pragma unroll
         for (int u = 0; u < G::QPT; ++u)
             if (t + u * NT < nq) D[t + u * NT] = pre[u];
@@ -454,7 +581,7 @@ __device__ __forceinline__ void inv2d_tile(const Pass2D& p, int64_t item, int64_
             const int rows = TH >> lev, cols = TW >> lev;
             const int rh = (int)ceil_shift(th, lev), rw = (int)ceil_shift(tw, lev);
             const int oh = (int)ceil_shift(th, lev - 1), ow = (int)ceil_shift(tw, lev - 1);
-            const float* in = (lev & 1) ? B : A;     // output of level lev+1
+            const float* lin = (lev & 1) ? B : A;     // output of level lev+1
             float* out = (lev & 1) ? A : B;
             const int pin = TW >> lev, pout = TW >> (lev - 1);
             const float* Dh = D + offs[lev];
@@ -462,7 +589,7 @@ __device__ __forceinline__ void inv2d_tile(const Pass2D& p, int64_t item, int64_
                 const int i = b / rw, k = b - i * rw;
                 const bool r1 = 2 * i + 1 < oh, c1 = 2 * k + 1 < ow;
                 const int e = i * cols + k;
-                const float ll = (lev == L) ? Dll[e] : in[i * pin + k];
+                const float ll = (lev == L) ? Dll[e] : lin[i * pin + k];
                 float x00, x01, x10, x11;
                 syn_edge(ll, Dh[e], Dh[rows * cols + e], Dh[2 * rows * cols + e], r1, c1, x00, x01,
                          x10, x11);
@@ -481,17 +608,44 @@ __device__ __forceinline__ void inv2d_tile(const Pass2D& p, int64_t item, int64_
     if (L >= 2) {
         float ll2[B2Y][B2X];
         const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
+        if (FULL && L >= 3) {
+            // walk the ancestor path: LL_L -> ... -> LL3 (one 2x2 synthesis
+            // butterfly per level, keeping the child on the path), then the
+            // level-3 butterfly gives this thread's LL2 entries
+            const int64_t R3 = R >> 1, C3 = C >> 1;
+            float ll = in.walk[0];
 #pragma unroll
-        for (int i = 0; i < B2Y; ++i)
+            for (int jj = 2; jj >= 1; --jj) {
+                const int j = 3 + jj;               // level j -> level j-1 (j = 5, 4)
+                if (j <= L) {
+                    const int dy = (int)((R3 >> (j - 4)) & 1), dx = (int)((C3 >> (j - 4)) & 1);
+                    const float hl = in.walk[1 + 3 * jj], lh = in.walk[2 + 3 * jj],
+                                hh = in.walk[3 + 3 * jj];
+                    const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
+                    ll = 0.5f * (dx ? base + tt : base - tt);
+                }
+            }
+            const float hl = in.walk[1], lh = in.walk[2], hh = in.walk[3];   // level 3
+            const int dy = (int)(R & 1);
 #pragma unroll
             for (int k = 0; k < B2X; ++k) {
-                const int lr = (lr0 >> 2) + i, lc = (lc0 >> 2) + k;
-                const bool ok = FULL || (lr < th2 && lc < tw2);
-                if (L >= 3)
-                    ll2[i][k] = ok ? A[lr * (TW / 4) + lc] : 0.0f;
-                else
-                    ll2[i][k] = ok ? ld1<SL>(llp + (R + i) * lp + C + k) : 0.0f;
+                const int dx = (int)((C + k) & 1);
+                const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
+                ll2[0][k] = 0.5f * (dx ? base + tt : base - tt);
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < B2Y; ++i)
+#pragma unroll
+                for (int k = 0; k < B2X; ++k) {
+                    const int lr = (lr0 >> 2) + i, lc = (lc0 >> 2) + k;
+                    const bool ok = FULL || (lr < th2 && lc < tw2);
+                    if (L >= 3)
+                        ll2[i][k] = ok ? A[lr * (TW / 4) + lc] : 0.0f;
+                    else
+                        ll2[i][k] = ok ? ld1<SL>(llp + (R + i) * lp + C + k) : 0.0f;
+                }
+        }
 #pragma unroll
         for (int i = 0; i < B2Y; ++i)
 #pragma unroll
@@ -581,72 +735,125 @@ __device__ __forceinline__ void tile_coords(const Pass2D& p, int64_t tile, int64
     }
 }
 
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE>
+// Interior launches are persistent and software pipelined: a work-group
+// walks tiles b, b + G, b + 2G, ... and issues the HBM reads of its next tile
+// before it computes and writes the current one, so that reads stay in
+// flight while the tile's LDS levels and stores run.  Edge launches process
+// one tile per work-group on the scalar path.
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE, bool PIPE>
 __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D p, int64_t ntiles) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
     __shared__ float sm[G::SMEM];
     const bool remap = p.remap && (int64_t)gridDim.x == ntiles;
-    for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
-        int64_t item, ty, tx;
-        tile_coords<EDGE>(p, remap ? xcd_tile(b, ntiles) : b, item, ty, tx);
-        fwd2d_tile<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, sm);
-        if (b + gridDim.x < ntiles) __syncthreads();
+    int64_t b = blockIdx.x;
+    if (b >= ntiles) return;
+    int64_t item, ty, tx;
+    tile_coords<EDGE>(p, remap ? xcd_tile(b, ntiles) : b, item, ty, tx);
+    FwdIn<RY, RX> cur;
+    fwd2d_load<SX, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, cur);
+    while (true) {
+        const int64_t nb = b + gridDim.x;
+        int64_t nitem = 0, nty = 0, ntx = 0;
+        FwdIn<RY, RX> nxt;
+        if (PIPE && nb < ntiles) {
+            tile_coords<EDGE>(p, nb, nitem, nty, ntx);
+            fwd2d_load<SX, RY, RX, GY, GX, !EDGE>(p, nitem, nty, ntx, nxt);
+        }
+        fwd2d_body<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, cur, sm);
+        if (nb >= ntiles) break;
+        __syncthreads();
+        if (!PIPE) {
+            tile_coords<EDGE>(p, nb, nitem, nty, ntx);
+            fwd2d_load<SX, RY, RX, GY, GX, !EDGE>(p, nitem, nty, ntx, nxt);
+        }   // LDS reuse by the next tile
+        cur = nxt;
+        b = nb;
+        item = nitem;
+        ty = nty;
+        tx = ntx;
     }
 }
 
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE>
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE, bool PIPE>
 __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D p, int64_t ntiles) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
+    using In = InvInT<SX, SD, SL, RY, RX, GY, GX>;
     __shared__ float sm[G::AN + G::BN + G::QPT * G::NT];
     const bool remap = p.remap && (int64_t)gridDim.x == ntiles;
-    for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
-        int64_t item, ty, tx;
-        tile_coords<EDGE>(p, remap ? xcd_tile(b, ntiles) : b, item, ty, tx);
-        inv2d_tile<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, sm);
-        if (b + gridDim.x < ntiles) __syncthreads();
+    int64_t b = blockIdx.x;
+    if (b >= ntiles) return;
+    int64_t item, ty, tx;
+    tile_coords<EDGE>(p, remap ? xcd_tile(b, ntiles) : b, item, ty, tx);
+    In cur;
+    inv2d_load<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, cur);
+    while (true) {
+        const int64_t nb = b + gridDim.x;
+        int64_t nitem = 0, nty = 0, ntx = 0;
+        In nxt;
+        if (PIPE && nb < ntiles) {
+            tile_coords<EDGE>(p, nb, nitem, nty, ntx);
+            inv2d_load<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, nitem, nty, ntx, nxt);
+        }
+        inv2d_body<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, cur, sm);
+        if (nb >= ntiles) break;
+        __syncthreads();
+        if (!PIPE) {
+            tile_coords<EDGE>(p, nb, nitem, nty, ntx);
+            inv2d_load<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, nitem, nty, ntx, nxt);
+        }
+        cur = nxt;
+        b = nb;
+        item = nitem;
+        ty = nty;
+        tx = ntx;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Tile-shape table and launchers
 // ---------------------------------------------------------------------------
-// Index -> (GY, GX, XCD remap); RY = 4 and RX = 16 bytes / element size.
-#define HAAR_2D_TILES(X) \
-    X(0, 8, 32, 1)       \
-    X(1, 8, 32, 0)       \
-    X(2, 8, 64, 1)       \
-    X(3, 8, 64, 0)       \
-    X(4, 8, 16, 1)       \
-    X(5, 16, 16, 1)
+// Index -> (GY, GX, XCD remap, work-groups per CU); RY = 4 and RX = 16 bytes
+// / element size.  Work-groups per CU = 0: one tile per work-group; k > 0: a
+// persistent interior grid of k work-groups per compute unit.
+#define HAAR_2D_TILES(X)   \
+    X(0, 8, 32, 0, 0)      \
+    X(1, 8, 64, 0, 0)      \
+    X(2, 8, 32, 0, 4)      \
+    X(3, 8, 64, 0, 2)      \
+    X(4, 8, 32, 0, 2)      \
+    X(5, 8, 32, 1, 0)      \
+    X(6, 8, 16, 0, 8)      \
+    X(7, 16, 16, 1, 0)
 
-int num_tile_configs_2d(int) { return 6; }
+int num_tile_configs_2d(int) { return 8; }
 
 Tile2D tile_config_2d(int elem_bytes, int index) {
     const int rx = 16 / elem_bytes;
     switch (index) {
-#define X(I, GY_, GX_, RM_) \
-    case I:                 \
-        return Tile2D{4, rx, GY_, GX_, RM_};
+#define X(I, GY_, GX_, RM_, WPC_) \
+    case I:                       \
+        return Tile2D{4, rx, GY_, GX_, RM_, WPC_};
         HAAR_2D_TILES(X)
 #undef X
         default:
-            return Tile2D{4, rx, 8, 32, 1};
+            return Tile2D{4, rx, 8, 32, 0, 0};
     }
 }
 
-template <class SX, class SD, class SL, int GY, int GX>
+template <class SX, class SD, class SL, int GY, int GX, bool PIPE>
 static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     constexpr int RX = 16 / SX::kBytes;
     constexpr int64_t kMaxGrid = 1 << 20;
     const int64_t interior = p.vec_ok ? p.full_x * p.full_y * p.batch : 0;
     const int64_t edge = p.total_tiles - interior;
     if (interior > 0) {
-        const unsigned grid = (unsigned)(interior < kMaxGrid ? interior : kMaxGrid);
+        const int64_t cap = p.persist > 0 ? p.persist : kMaxGrid;
+        const unsigned grid = (unsigned)(interior < cap ? interior : cap);
         if (inverse)
-            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, false>), dim3(grid),
+            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE>), dim3(grid),
                                dim3(GY * GX), 0, s, p, interior);
         else
-            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, false>), dim3(grid),
+            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE>), dim3(grid),
                                dim3(GY * GX), 0, s, p, interior);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -654,10 +861,10 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     if (edge > 0) {
         const unsigned grid = (unsigned)(edge < kMaxGrid ? edge : kMaxGrid);
         if (inverse)
-            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, true>), dim3(grid),
+            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, true, false>), dim3(grid),
                                dim3(GY * GX), 0, s, p, edge);
         else
-            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, true>), dim3(grid),
+            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, true, false>), dim3(grid),
                                dim3(GY * GX), 0, s, p, edge);
         return hipGetLastError();
     }
@@ -667,13 +874,13 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
 template <class S>
 static hipError_t dispatch2d(const Pass2D& p, int cfg, bool inverse, hipStream_t s) {
     switch (cfg) {
-#define X(I, GY_, GX_, RM_) \
-    case I:                 \
-        return launch2d<S, S, S, GY_, GX_>(p, inverse, s);
+#define X(I, GY_, GX_, RM_, WPC_) \
+    case I:                       \
+        return launch2d<S, S, S, GY_, GX_, (WPC_ > 0)>(p, inverse, s);
         HAAR_2D_TILES(X)
 #undef X
         default:
-            return launch2d<S, S, S, 8, 32>(p, inverse, s);
+            return launch2d<S, S, S, 8, 32, false>(p, inverse, s);
     }
 }
 
@@ -683,9 +890,9 @@ static hipError_t dispatch2d(const Pass2D& p, int cfg, bool inverse, hipStream_t
 template <class S>
 static hipError_t dispatch2d_mixed(const Pass2D& p, bool x_f32, bool ll_f32, bool inverse,
                                    hipStream_t s) {
-    if (x_f32 && ll_f32) return launch2d<StF32, S, StF32, 8, 32>(p, inverse, s);
-    if (x_f32) return launch2d<StF32, S, S, 8, 32>(p, inverse, s);
-    return launch2d<S, S, StF32, 8, 32>(p, inverse, s);
+    if (x_f32 && ll_f32) return launch2d<StF32, S, StF32, 8, 32, false>(p, inverse, s);
+    if (x_f32) return launch2d<StF32, S, S, 8, 32, false>(p, inverse, s);
+    return launch2d<S, S, StF32, 8, 32, false>(p, inverse, s);
 }
 
 static hipError_t dispatch2d_dtype(const Pass2D& p, int dtype, int cfg, bool x_f32, bool ll_f32,

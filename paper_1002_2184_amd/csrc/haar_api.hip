@@ -47,6 +47,20 @@ int max_levels(int64_t n) {
 
 bool aligned(const void* p, int a) { return ((uintptr_t)p % (uintptr_t)a) == 0; }
 
+// Compute units of the current device (queried once per device).
+int device_cus() {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
 static bool ranges_overlap(const void* a, const void* b, uint64_t bytes) {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
     return x < y + bytes && y < x + bytes;
@@ -172,6 +186,7 @@ int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch
         const Tile2D tc = tile_config_2d(ebx, pcfg);
         tile_grid(p, tc);
         p.remap = tc.remap;
+        p.persist = tc.wg_per_cu > 0 ? (int64_t)tc.wg_per_cu * device_cus() : 0;
         p.vec_ok = vec_ok_2d(p, inverse, ebx, ebl);
         hipError_t e = inverse ? launch_inv2d(p, dtype, pcfg, x_f32, ll_f32, s)
                                : launch_fwd2d(p, dtype, pcfg, x_f32, ll_f32, s);

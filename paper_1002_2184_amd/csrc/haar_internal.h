@@ -12,6 +12,7 @@ int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);
 int max_levels(int64_t n);
 bool aligned(const void* p, int a);
+int device_cus();
 
 // HAAR_FAULT_INJECT=launch makes every transform call fail as if its launch
 // had failed (HAAR_ERR_HIP) before anything is enqueued: a host-side way to

@@ -21,6 +21,7 @@ struct Pass2D {
     int64_t tiles_x, tiles_y, tiles_per_item, total_tiles;
     int64_t full_x, full_y;                 // tiles that lie entirely inside the region
     int32_t remap;                          // deal contiguous tile ranges to each XCD
+    int64_t persist;                        // interior grid size (0 = one tile per work-group)
 };
 
 // One fused 1D pass: `levels` levels on a length-n region (chunks of C).
@@ -41,6 +42,7 @@ struct Pass1D {
 struct Tile2D {
     int ry, rx, gy, gx;
     int remap;
+    int wg_per_cu;                          // persistent interior grid: work-groups per CU
     int th() const { return gy * ry; }
     int tw() const { return gx * rx; }
     int threads() const { return gy * gx; }

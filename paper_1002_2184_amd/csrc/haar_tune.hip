@@ -49,10 +49,10 @@ int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels) 
     if (dtype >= 0 && dtype < 3 && g_force_2d[dtype] >= 0) return g_force_2d[dtype];
     auto it = g_table.find(key_2d(dtype, inverse, h, w, levels));
     if (it != g_table.end()) return it->second;
-    // measured defaults (4096^2 FP32, 5 levels): the analysis streams best
-    // with blocks dealt round-robin, the synthesis with XCD-contiguous ranges
-    // (neighbouring tiles share the L2 lines of their small deep-level reads)
-    return inverse ? 0 : 1;
+    // measured default (4096^2 FP32, 5 levels, cold HBM): 32 x 256 tiles
+    // (4 x 4 registers per thread, 512 threads), one tile per work-group,
+    // blocks dealt round-robin to the XCDs
+    return 1;
 }
 
 int choose_config_1d(int dtype, bool inverse, int64_t n, int levels) {
@@ -127,8 +127,10 @@ const char* haar_tune_candidate_name(int32_t dtype, int32_t index) {
     if (dtype < 0 || dtype > 2 || index < 0 || index >= num_tile_configs_2d(elem_bytes(dtype)))
         return "";
     const Tile2D t = tile_config_2d(elem_bytes(dtype), index);
-    snprintf(buf, sizeof buf, "tile %dx%d, %d threads, %dx%d per thread%s", t.th(), t.tw(),
-             t.threads(), t.ry, t.rx, t.remap ? ", XCD-contiguous" : "");
+    char pers[32] = "";
+    if (t.wg_per_cu > 0) snprintf(pers, sizeof pers, ", persistent %d/CU", t.wg_per_cu);
+    snprintf(buf, sizeof buf, "tile %dx%d, %d threads, %dx%d per thread%s%s", t.th(), t.tw(),
+             t.threads(), t.ry, t.rx, t.remap ? ", XCD-contiguous" : "", pers);
     return buf;
 }
 
