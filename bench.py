@@ -32,7 +32,8 @@ H = W = 4096
 LEVELS = 5
 PEAK_GBPS = 8000.0          # MI355X HBM3E, 8 TB/s
 SETS = 4
-KERNEL_SOURCES = ["paper_1002_2184_amd/csrc/haar_2d.hip", "paper_1002_2184_amd/csrc/haar_device.h"]
+KERNEL_SOURCES = ["paper_1002_2184_amd/csrc/haar_2d.hip", "paper_1002_2184_amd/csrc/haar_2d_tile.h",
+                  "paper_1002_2184_amd/csrc/haar_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd2d_inv2d_4096x4096_L5.json")
 
 

@@ -117,30 +117,44 @@ int haar_max_levels_1d(int64_t length);
 int haar_max_levels_2d(int64_t height, int64_t width);
 
 /* ------------------------------------------------------------------------
- * Batched transforms of uneven sizes: one persistent launch per execute.
- * A plan holds host memory only.  Its device-side descriptor table and
- * counters live in a caller-owned workspace of haar_plan_workspace_size()
- * bytes (256-byte aligned).  haar_plan_upload() writes the table and zeroes
- * the counters (it enqueues copies: not allowed during stream capture);
- * haar_plan_execute() enqueues exactly one kernel, allocates nothing, never
- * synchronises and leaves the counters at zero when the kernel ends, so it
- * may be captured into a hipGraph and replayed.  Executions that share one
- * workspace must not overlap in time.  Item pointers are device pointers;
- * every item must satisfy the plain-call rules above (no aliasing).
+ * Batched transforms of uneven sizes (many signals or images of different
+ * lengths / shapes in one launch).
+ *
+ * A plan lists the work units of all items (2D: tiles, 1D: chunks of 4096
+ * samples), largest items first, and haar_plan_execute() enqueues ONE
+ * persistent kernel whose work-groups claim units with an atomic counter
+ * until the list is exhausted.  The plan itself holds host memory only; the
+ * device-side tables and counters live in a caller-owned workspace of
+ * haar_plan_workspace_size() bytes (256-byte aligned).
+ *
+ * haar_plan_upload() writes the tables and zeroes the counters (it enqueues a
+ * memset and copies from memory the plan owns: do not destroy the plan, and
+ * do not call it during stream capture, before the stream has passed them).
+ * haar_plan_execute() allocates nothing, never synchronises, and leaves the
+ * counters at zero when its kernel ends (the last work-group resets them), so
+ * it may be captured into a hipGraph and replayed.  Executions sharing one
+ * workspace must not overlap in time.  Item pointers are device pointers and
+ * follow the plain-call rules (same dtype for all items, no aliasing).
+ *
+ * Limits: 2D items 1 <= levels <= min(5, haar_max_levels_2d); 1D items
+ * 1 <= levels <= min(20, haar_max_levels_1d), and items with more than 12
+ * levels at most 1024 * 4096 samples long (HAAR_ERR_UNSUPPORTED otherwise).
+ * 1D items with more than 12 levels keep their level-12 approximation in the
+ * storage type between the on-chip stages.
  * ------------------------------------------------------------------------ */
 typedef struct {
-    const void* in;   /* [length] input (device)          */
-    void* out;        /* [length] output (device)         */
+    const void* in;   /* [length] input (device)                */
+    void* out;        /* [length] output (device)               */
     int64_t length;
-    int32_t levels;   /* 0 .. haar_max_levels_1d(length)  */
+    int32_t levels;
 } haar_item_1d;
 
 typedef struct {
-    const void* in;   /* [height][width] input (device)   */
-    void* out;        /* [height][width] output (device)  */
+    const void* in;   /* [height][width] input (device)         */
+    void* out;        /* [height][width] output (device)        */
     int64_t height;
     int64_t width;
-    int32_t levels;   /* 0 .. min(5, haar_max_levels_2d)  */
+    int32_t levels;
 } haar_item_2d;
 
 typedef struct haar_plan haar_plan;
@@ -153,8 +167,15 @@ int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype,
 int haar_plan_workspace_size(const haar_plan* plan, size_t* bytes);
 int haar_plan_upload(haar_plan* plan, void* workspace, void* stream);
 int haar_plan_execute(const haar_plan* plan, void* workspace, void* stream);
-/* Number of work tiles and the persistent grid size (work-groups). */
+/* Number of work units and the persistent grid size (work-groups). */
 int haar_plan_info(const haar_plan* plan, int64_t* tiles, int32_t* grid);
+/* Select the tile shape of a 2D plan (0: 32 rows x 16 vectors, 1: 32 rows x
+ * 32 vectors; 1D plans accept 0 only); the plan must be uploaded again. */
+int haar_plan_set_config(haar_plan* plan, int32_t config);
+/* Autotune a plan: time executes of every tile shape on `stream` (hipEvents;
+ * synchronises the stream; overwrites the items' outputs), keep the fastest,
+ * upload it, and return its index in *choice.  Not during capture. */
+int haar_plan_tune(haar_plan* plan, void* workspace, void* stream, int32_t* choice);
 int haar_plan_destroy(haar_plan* plan);
 
 /* ------------------------------------------------------------------------

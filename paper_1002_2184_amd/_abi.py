@@ -53,6 +53,8 @@ _SIGS = {
     "haar_plan_upload": ([_VP, _VP, _VP], ctypes.c_int),
     "haar_plan_execute": ([_VP, _VP, _VP], ctypes.c_int),
     "haar_plan_info": ([_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I32)], ctypes.c_int),
+    "haar_plan_set_config": ([_VP, _I32], ctypes.c_int),
+    "haar_plan_tune": ([_VP, _VP, _VP, ctypes.POINTER(_I32)], ctypes.c_int),
     "haar_plan_destroy": ([_VP], ctypes.c_int),
     "haar_tune_2d": ([_I32, _I32, _I64, _I64, _I32, _I64, _VP, _SZ, _VP, ctypes.POINTER(_I32)], ctypes.c_int),
     "haar_tune_1d": ([_I32, _I32, _I64, _I32, _I64, _VP, _SZ, _VP, ctypes.POINTER(_I32)], ctypes.c_int),
@@ -139,6 +141,14 @@ def haar_plan_execute(plan, workspace, stream=0):
 
 def haar_plan_info(plan, tiles, grid):
     return lib().haar_plan_info(plan, tiles, grid)
+
+
+def haar_plan_set_config(plan, config):
+    return lib().haar_plan_set_config(plan, config)
+
+
+def haar_plan_tune(plan, workspace, stream, choice):
+    return lib().haar_plan_tune(plan, workspace, stream, choice)
 
 
 def haar_plan_destroy(plan):

@@ -1,702 +1,9 @@
-// Fused separable 2D Haar analysis / synthesis kernels for gfx950.
-//
-// One work-group owns one TH x TW tile of the region (TH, TW multiples of
-// 32 = 2^5, the largest dependency block of one pass), so a tile needs no
-// halo and crosses HBM once: read once, every band written once.
-//
-// Per thread: an RY x RX register block (16 bytes per row: 4 x f32 or
-// 8 x bf16/f16).  Levels 1 and 2 run in registers on 2x2 blocks
-// (Eq. (11)-(12) along the width, then along the height, fused into one
-// butterfly per 2x2 block with the exact factor 1/2 = b00^2); deeper levels
-// of the pass run in LDS on the tile's LL2 region.  The approximation path of
-// the analysis carries compensated FP32 pairs.
-//
-// Interior tiles whose rows and band origins are 16-byte aligned take the
-// vector path (FULL = true).  Edge tiles and unaligned layouts take the same
-// code with per-element validity (FULL = false), where the odd-size carry
-// rule applies: at an odd row/column count the last row/column passes
-// unscaled into the approximation.
-#include "haar_device.h"
-#include "haar_kernels.h"
+// Kernels and launchers of the plain 2D transforms (device code of one
+// tile: haar_2d_tile.h).
+#include "haar_2d_tile.h"
 
 namespace haar {
 
-// ---------------------------------------------------------------------------
-// 2x2 butterflies
-// ---------------------------------------------------------------------------
-// Analysis of a full 2x2 block of exact floats (x00 x01 / x10 x11).
-__device__ __forceinline__ void ana_full_f(float x00, float x01, float x10, float x11, df& ll,
-                                           float& hl, float& lh, float& hh) {
-    ll = df_scale(df_sum4f(x00, x01, x10, x11), 0.5f);
-    const float dr0 = x01 - x00, dr1 = x11 - x10;   // high along width, rows 0/1
-    hl = 0.5f * (dr0 + dr1);
-    hh = 0.5f * (dr1 - dr0);
-    lh = 0.5f * ((x10 - x00) + (x11 - x01));
-}
-
-// Analysis of a full 2x2 block of pairs.
-__device__ __forceinline__ void ana_full_df(df x00, df x01, df x10, df x11, df& ll, float& hl,
-                                            float& lh, float& hh) {
-    ll = df_scale(df_sum4(x00, x01, x10, x11), 0.5f);
-    const float dr0 = df_diff(x01, x00), dr1 = df_diff(x11, x10);
-    hl = 0.5f * (dr0 + dr1);
-    hh = 0.5f * (dr1 - dr0);
-    lh = 0.5f * (df_diff(x10, x00) + df_diff(x11, x01));
-}
-
-// Analysis with the carry rule.  c1: column 2k+1 exists; r1: row 2i+1 exists.
-__device__ __forceinline__ void ana_edge_df(df x00, df x01, df x10, df x11, bool r1, bool c1,
-                                            df& ll, float& hl, float& lh, float& hh) {
-    if (r1 && c1) {
-        ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
-    } else if (c1) {            // single row: row pass only, column carried
-        ll = df_rs2(df_add(x00, x01));
-        hl = df_round(df_rs2(df_from(df_diff(x01, x00))));
-        lh = hh = 0.0f;
-    } else if (r1) {            // single column: column pass only, row carried
-        ll = df_rs2(df_add(x00, x10));
-        lh = df_round(df_rs2(df_from(df_diff(x10, x00))));
-        hl = hh = 0.0f;
-    } else {
-        ll = x00;
-        hl = lh = hh = 0.0f;
-    }
-}
-
-// Synthesis of one 2x2 block (inverse of the analysis), with the carry rule.
-__device__ __forceinline__ void syn_edge(float ll, float hl, float lh, float hh, bool r1, bool c1,
-                                         float& x00, float& x01, float& x10, float& x11) {
-    if (r1 && c1) {
-        const float p = ll - lh, q = ll + lh, r = hl - hh, u = hl + hh;
-        x00 = 0.5f * (p - r);
-        x01 = 0.5f * (p + r);
-        x10 = 0.5f * (q - u);
-        x11 = 0.5f * (q + u);
-    } else if (c1) {
-        x00 = (ll - hl) * kRs2Hi;
-        x01 = (ll + hl) * kRs2Hi;
-        x10 = x11 = 0.0f;
-    } else if (r1) {
-        x00 = (ll - lh) * kRs2Hi;
-        x10 = (ll + lh) * kRs2Hi;
-        x01 = x11 = 0.0f;
-    } else {
-        x00 = ll;
-        x01 = x10 = x11 = 0.0f;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Analysis tile
-// ---------------------------------------------------------------------------
-// SX: storage of the region (input of the analysis, output of the synthesis),
-// SD: storage of the detail bands, SL: storage of the pass's deepest LL.
-// They differ only when a deep transform keeps an intermediate approximation
-// in FP32 scratch between passes.
-template <class SX, int RY, int RX, int GY, int GX>
-struct Geo2D {
-    static constexpr int NT = GY * GX, TH = GY * RY, TW = GX * RX;
-    static constexpr int B1Y = RY / 2, B1X = RX / 2, B2Y = RY / 4, B2X = RX / 4;
-    static constexpr int AN = (TH / 4) * (TW / 4);   // LDS buffer A: LL2 region
-    static constexpr int BN = (TH / 8) * (TW / 8);   // LDS buffer B: LL3 region
-    static constexpr int SMEM = 2 * AN + 2 * BN;     // floats (hi + lo each)
-    // synthesis: LL_L and the detail bands of levels 3..L (L <= 5) of one tile
-    static constexpr int R3 = (TH >> 3) * (TW >> 3), R4 = (TH >> 4) * (TW >> 4), R5 = (TH >> 5) * (TW >> 5);
-    static constexpr int QMAX = 3 * (R3 + R4 + R5) + R3;      // >= the count for any L <= 5
-    static constexpr int QPT = (QMAX + NT - 1) / NT;           // prefetched values per thread
-    static_assert(RY == 4 && RX * SX::kBytes == 16, "register block is 4 rows x 16 bytes");
-    static_assert(TH % 32 == 0 && TW % 32 == 0, "tile must hold whole 32x32 blocks");
-};
-
-// Register block of one analysis tile: the RY x RX input samples of a thread.
-template <int RY, int RX>
-struct FwdIn {
-    float v[RY][RX];
-};
-
-template <class SX, int RY, int RX, int GY, int GX, bool FULL>
-__device__ __forceinline__ void fwd2d_load(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
-                                           FwdIn<RY, RX>& in) {
-    using G = Geo2D<SX, RY, RX, GY, GX>;
-    constexpr int TH = G::TH, TW = G::TW;
-    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
-    const int64_t r0 = ty * TH, c0 = tx * TW;
-    const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
-    const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
-    const int lr0 = rg * RY, lc0 = cg * RX;
-    const typename SX::raw* src =
-        reinterpret_cast<const typename SX::raw*>(p.src) + item * p.src_bstride + r0 * p.src_pitch + c0;
-    if constexpr (FULL) {
-#pragma unroll
-        for (int r = 0; r < RY; ++r) ld_vec<SX, RX>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0, in.v[r]);
-    } else {
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int c = 0; c < RX; ++c)
-                in.v[r][c] = (lr0 + r < th && lc0 + c < tw)
-                                 ? ld1<SX>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0 + c)
-                                 : 0.0f;
-    }
-}
-
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
-__device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
-                                           const FwdIn<RY, RX>& in, float* sm) {
-    using G = Geo2D<SX, RY, RX, GY, GX>;
-    constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
-    constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
-
-    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
-    const int64_t r0 = ty * TH, c0 = tx * TW;
-    const int L = p.levels;
-    const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
-    const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
-    const int lr0 = rg * RY, lc0 = cg * RX;            // local origin of this thread's block
-
-    typename SD::raw* det = reinterpret_cast<typename SD::raw*>(p.det) + item * p.det_bstride;
-    typename SL::raw* llp = reinterpret_cast<typename SL::raw*>(p.ll) + item * p.ll_bstride;
-    const int64_t dp = p.det_pitch, lp = p.ll_pitch;
-    const auto& v = in.v;
-
-    // ---- level 1 (registers)
-    df a1[B1Y][B1X];
-    {
-        float hl[B1Y][B1X], lh[B1Y][B1X], hh[B1Y][B1X];
-#pragma unroll
-        for (int i = 0; i < B1Y; ++i)
-#pragma unroll
-            for (int k = 0; k < B1X; ++k) {
-                if constexpr (FULL) {
-                    ana_full_f(v[2 * i][2 * k], v[2 * i][2 * k + 1], v[2 * i + 1][2 * k],
-                               v[2 * i + 1][2 * k + 1], a1[i][k], hl[i][k], lh[i][k], hh[i][k]);
-                } else {
-                    const bool r1 = lr0 + 2 * i + 1 < th, c1 = lc0 + 2 * k + 1 < tw;
-                    ana_edge_df(df_from(v[2 * i][2 * k]), df_from(v[2 * i][2 * k + 1]),
-                                df_from(v[2 * i + 1][2 * k]), df_from(v[2 * i + 1][2 * k + 1]), r1,
-                                c1, a1[i][k], hl[i][k], lh[i][k], hh[i][k]);
-                }
-            }
-        const int64_t hs = ceil_shift(p.h, 1), ws = ceil_shift(p.w, 1);
-        const int64_t R = (r0 >> 1) + (lr0 >> 1), C = (c0 >> 1) + (lc0 >> 1);
-        if constexpr (FULL) {
-#pragma unroll
-            for (int i = 0; i < B1Y; ++i) {
-                st_vec<SD, B1X>(det + (R + i) * dp + ws + C, hl[i]);
-                st_vec<SD, B1X>(det + (hs + R + i) * dp + C, lh[i]);
-                st_vec<SD, B1X>(det + (hs + R + i) * dp + ws + C, hh[i]);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < B1Y; ++i)
-#pragma unroll
-                for (int k = 0; k < B1X; ++k) {
-                    const int lr = lr0 + 2 * i, lc = lc0 + 2 * k;
-                    if (lr < th && lc < tw) {
-                        const bool r1 = lr + 1 < th, c1 = lc + 1 < tw;
-                        if (c1) st1<SD>(det + (R + i) * dp + ws + C + k, hl[i][k]);
-                        if (r1) st1<SD>(det + (hs + R + i) * dp + C + k, lh[i][k]);
-                        if (r1 && c1) st1<SD>(det + (hs + R + i) * dp + ws + C + k, hh[i][k]);
-                    }
-                }
-        }
-        if (L == 1) {
-#pragma unroll
-            for (int i = 0; i < B1Y; ++i) {
-                if constexpr (FULL) {
-                    float o[B1X];
-#pragma unroll
-                    for (int k = 0; k < B1X; ++k) o[k] = df_round(a1[i][k]);
-                    st_vec<SL, B1X>(llp + (R + i) * lp + C, o);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < B1X; ++k)
-                        if (lr0 + 2 * i < th && lc0 + 2 * k < tw)
-                            st1<SL>(llp + (R + i) * lp + C + k, df_round(a1[i][k]));
-                }
-            }
-            return;
-        }
-    }
-
-    // ---- level 2 (registers)
-    df a2[B2Y][B2X];
-    {
-        float hl[B2Y][B2X], lh[B2Y][B2X], hh[B2Y][B2X];
-        const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
-        const int l1r = lr0 >> 1, l1c = lc0 >> 1;       // local level-1 origin
-#pragma unroll
-        for (int i = 0; i < B2Y; ++i)
-#pragma unroll
-            for (int k = 0; k < B2X; ++k) {
-                if constexpr (FULL) {
-                    ana_full_df(a1[2 * i][2 * k], a1[2 * i][2 * k + 1], a1[2 * i + 1][2 * k],
-                                a1[2 * i + 1][2 * k + 1], a2[i][k], hl[i][k], lh[i][k], hh[i][k]);
-                } else {
-                    const bool r1 = l1r + 2 * i + 1 < th1, c1 = l1c + 2 * k + 1 < tw1;
-                    ana_edge_df(a1[2 * i][2 * k], a1[2 * i][2 * k + 1], a1[2 * i + 1][2 * k],
-                                a1[2 * i + 1][2 * k + 1], r1, c1, a2[i][k], hl[i][k], lh[i][k],
-                                hh[i][k]);
-                }
-            }
-        const int64_t hs = ceil_shift(p.h, 2), ws = ceil_shift(p.w, 2);
-        const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
-        if constexpr (FULL) {
-#pragma unroll
-            for (int i = 0; i < B2Y; ++i) {
-                st_vec<SD, B2X>(det + (R + i) * dp + ws + C, hl[i]);
-                st_vec<SD, B2X>(det + (hs + R + i) * dp + C, lh[i]);
-                st_vec<SD, B2X>(det + (hs + R + i) * dp + ws + C, hh[i]);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < B2Y; ++i)
-#pragma unroll
-                for (int k = 0; k < B2X; ++k) {
-                    const int lr = l1r + 2 * i, lc = l1c + 2 * k;
-                    if (lr < th1 && lc < tw1) {
-                        const bool r1 = lr + 1 < th1, c1 = lc + 1 < tw1;
-                        if (c1) st1<SD>(det + (R + i) * dp + ws + C + k, hl[i][k]);
-                        if (r1) st1<SD>(det + (hs + R + i) * dp + C + k, lh[i][k]);
-                        if (r1 && c1) st1<SD>(det + (hs + R + i) * dp + ws + C + k, hh[i][k]);
-                    }
-                }
-        }
-        if (L == 2) {
-#pragma unroll
-            for (int i = 0; i < B2Y; ++i) {
-                if constexpr (FULL) {
-                    float o[B2X];
-#pragma unroll
-                    for (int k = 0; k < B2X; ++k) o[k] = df_round(a2[i][k]);
-                    st_vec<SL, B2X>(llp + (R + i) * lp + C, o);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < B2X; ++k)
-                        if (l1r + 2 * i < th1 && l1c + 2 * k < tw1)
-                            st1<SL>(llp + (R + i) * lp + C + k, df_round(a2[i][k]));
-                }
-            }
-            return;
-        }
-    }
-
-    // ---- levels 3..L.  Buffer A holds LL2 (pitch TW/4), buffer B LL3 (pitch TW/8).
-    float* Ahi = sm;
-    float* Alo = sm + G::AN;
-    float* Bhi = sm + 2 * G::AN;
-    float* Blo = Bhi + G::BN;
-    int rh = (th + 3) >> 2, rw = (tw + 3) >> 2;   // local region size at level 2
-    int first = 3;                                // first level of the single-wave phase
-    if constexpr (FULL && GX == 32) {
-        // Level 3 inside each wavefront: with 32 column groups a wave holds
-        // LL2 rows 2w (lanes 0-31) and 2w+1 (lanes 32-63), so every 2x2 block
-        // of LL2 lies in one wave: xor-shuffles fetch the partners.
-        const int lane = t & 63, w = t >> 6;
-        df x00, x01, x10, x11;
-        if constexpr (B2X == 1) {
-            const df a = a2[0][0];
-            x00 = a;
-            x01 = df{__shfl_xor(a.hi, 1), __shfl_xor(a.lo, 1)};
-            x10 = df{__shfl_xor(a.hi, 32), __shfl_xor(a.lo, 32)};
-            x11 = df{__shfl_xor(a.hi, 33), __shfl_xor(a.lo, 33)};
-        } else {
-            x00 = a2[0][0];
-            x01 = a2[0][1];
-            x10 = df{__shfl_xor(a2[0][0].hi, 32), __shfl_xor(a2[0][0].lo, 32)};
-            x11 = df{__shfl_xor(a2[0][1].hi, 32), __shfl_xor(a2[0][1].lo, 32)};
-        }
-        const bool active = B2X == 1 ? (lane & 33) == 0 : lane < 32;
-        if (active) {
-            const int k = B2X == 1 ? (lane >> 1) : lane;     // level-3 column in the tile
-            df ll;
-            float hl, lh, hh;
-            ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
-            const int64_t hs = ceil_shift(p.h, 3), ws = ceil_shift(p.w, 3);
-            const int64_t R = (r0 >> 3) + w, C = (c0 >> 3) + k;
-            st1<SD>(det + R * dp + ws + C, hl);
-            st1<SD>(det + (hs + R) * dp + C, lh);
-            st1<SD>(det + (hs + R) * dp + ws + C, hh);
-            if (L == 3) {
-                st1<SL>(llp + R * lp + C, df_round(ll));
-            } else {
-                Bhi[w * (TW / 8) + k] = ll.hi;
-                Blo[w * (TW / 8) + k] = ll.lo;
-            }
-        }
-        if (L == 3) return;
-        rh = TH / 8;
-        rw = TW / 8;
-        first = 4;
-    } else {
-#pragma unroll
-        for (int i = 0; i < B2Y; ++i)
-#pragma unroll
-            for (int k = 0; k < B2X; ++k) {
-                const int idx = ((lr0 >> 2) + i) * (TW / 4) + (lc0 >> 2) + k;
-                Ahi[idx] = a2[i][k].hi;
-                Alo[idx] = a2[i][k].lo;
-            }
-    }
-    __syncthreads();
-
-    // The remaining levels are small (at most (TH/8) x (TW/8) blocks): the
-    // first wavefront does them alone, ordered by wavefront-level barriers, so
-    // the other wavefronts of the work-group can retire.
-    if (t >= 64) return;
-    for (int lev = first; lev <= L; ++lev) {
-        const bool odd = lev & 1;
-        const float* ihi = odd ? Ahi : Bhi;
-        const float* ilo = odd ? Alo : Blo;
-        float* ohi = odd ? Bhi : Ahi;
-        float* olo = odd ? Blo : Alo;
-        const int pin = TW >> (lev - 1), pout = TW >> lev;
-        const int bh = (rh + 1) >> 1, bw = (rw + 1) >> 1;
-        const int64_t hs = ceil_shift(p.h, lev), ws = ceil_shift(p.w, lev);
-        const int64_t R0 = r0 >> lev, C0 = c0 >> lev;
-        for (int b = t; b < bh * bw; b += 64) {
-            const int i = b / bw, k = b - i * bw;
-            const bool r1 = 2 * i + 1 < rh, c1 = 2 * k + 1 < rw;
-            const int i0 = (2 * i) * pin + 2 * k;
-            const df x00 = {ihi[i0], ilo[i0]};
-            const df x01 = c1 ? df{ihi[i0 + 1], ilo[i0 + 1]} : df{0.0f, 0.0f};
-            const df x10 = r1 ? df{ihi[i0 + pin], ilo[i0 + pin]} : df{0.0f, 0.0f};
-            const df x11 = (r1 && c1) ? df{ihi[i0 + pin + 1], ilo[i0 + pin + 1]} : df{0.0f, 0.0f};
-            df ll;
-            float hl, lh, hh;
-            ana_edge_df(x00, x01, x10, x11, r1, c1, ll, hl, lh, hh);
-            const int64_t R = R0 + i, C = C0 + k;
-            if (c1) st1<SD>(det + R * dp + ws + C, hl);
-            if (r1) st1<SD>(det + (hs + R) * dp + C, lh);
-            if (r1 && c1) st1<SD>(det + (hs + R) * dp + ws + C, hh);
-            if (lev == L) {
-                st1<SL>(llp + R * lp + C, df_round(ll));
-            } else {
-                ohi[i * pout + k] = ll.hi;
-                olo[i * pout + k] = ll.lo;
-            }
-        }
-        rh = bh;
-        rw = bw;
-        if (lev < L) {   // LDS written by some lanes, read by others of this wavefront
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Synthesis tile
-// ---------------------------------------------------------------------------
-// Everything one thread of a synthesis tile reads from HBM: its share of the
-// small levels (LL_L and the bands of levels 3..L, one flat index space:
-// level by level HL, LH, HH, then LL_L) and the level-1/2 details of its
-// register block.
-template <int QPT, int B1Y, int B1X, int B2Y, int B2X>
-struct InvIn {
-    float pre[QPT];      // edge tiles: share of the small levels, staged through LDS
-    float walk[10];      // interior tiles: LL_L, then (HL, LH, HH) of levels 3, 4, 5 on the
-                         // ancestor path of this thread's LL3 coefficient
-    float hl1[B1Y][B1X], lh1[B1Y][B1X], hh1[B1Y][B1X];
-    float hl2[B2Y][B2X], lh2[B2Y][B2X], hh2[B2Y][B2X];
-};
-
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX>
-using InvInT = InvIn<Geo2D<SX, RY, RX, GY, GX>::QPT, RY / 2, RX / 2, RY / 4, RX / 4>;
-
-// number of prefetched small-level values of a tile of L levels (L >= 3)
-template <int TH, int TW>
-__device__ __forceinline__ int small_count(int L) {
-    int off = 0;
-    for (int lev = 3; lev <= L; ++lev) off += 3 * (TH >> lev) * (TW >> lev);
-    return off + (TH >> L) * (TW >> L);
-}
-
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
-__device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
-                                           InvInT<SX, SD, SL, RY, RX, GY, GX>& in) {
-    using G = Geo2D<SX, RY, RX, GY, GX>;
-    constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
-    constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
-    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
-    const int64_t r0 = ty * TH, c0 = tx * TW;
-    const int L = p.levels;
-    const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
-    const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
-    const int lr0 = rg * RY, lc0 = cg * RX;
-    const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
-    const typename SD::raw* det = reinterpret_cast<const typename SD::raw*>(p.det) + item * p.det_bstride;
-    const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
-    const int64_t dp = p.det_pitch, lp = p.ll_pitch;
-
-    // ---- interior tiles: the ancestor path of this thread's LL3 coefficient,
-    // LL_L then (HL, LH, HH) of levels L..3, loaded first (many lanes share
-    // these addresses, so most requests hit in cache)
-    if (FULL && L >= 3) {
-        const int64_t R3 = ((r0 >> 2) + (lr0 >> 2)) >> 1, C3 = ((c0 >> 2) + (lc0 >> 2)) >> 1;
-        in.walk[0] = ld1<SL>(llp + (R3 >> (L - 3)) * lp + (C3 >> (L - 3)));
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
-            const int j = 3 + jj;
-            if (j <= L) {
-                const int64_t hs = ceil_shift(p.h, j), ws = ceil_shift(p.w, j);
-                const int64_t R = R3 >> (j - 3), C = C3 >> (j - 3);
-                in.walk[1 + 3 * jj] = ld1<SD>(det + R * dp + ws + C);
-                in.walk[2 + 3 * jj] = ld1<SD>(det + (hs + R) * dp + C);
-                in.walk[3 + 3 * jj] = ld1<SD>(det + (hs + R) * dp + ws + C);
-            }
-        }
-    }
-    // ---- edge tiles: small levels first, so that they are the first to arrive
-    if (!FULL && L >= 3) {
-#pragma unroll
-        for (int u = 0; u < G::QPT; ++u) {
-            const int q = t + u * NT;
-            in.pre[u] = 0.0f;
-            int off = 0;
-            for (int lev = 3; lev <= L + 1; ++lev) {
-                const int lv = lev <= L ? lev : L;
-                const int rows = TH >> lv, cols = TW >> lv;
-                const int cnt = lev <= L ? 3 * rows * cols : rows * cols;
-                if (q >= off && q < off + cnt) {
-                    const int e = q - off;
-                    const int band = lev <= L ? e / (rows * cols) : 3;   // 3 = LL_L
-                    const int ij = e - (lev <= L ? band : 0) * rows * cols;
-                    const int i = ij / cols, k = ij - i * cols;
-                    const int oh = (int)ceil_shift(th, lv - 1), ow = (int)ceil_shift(tw, lv - 1);
-                    const int rh = (int)ceil_shift(th, lv), rw = (int)ceil_shift(tw, lv);
-                    const int64_t hs = ceil_shift(p.h, lv), ws = ceil_shift(p.w, lv);
-                    const int64_t R = (r0 >> lv) + i, C = (c0 >> lv) + k;
-                    if (band == 0) {          // HL: rows of LL_lv, odd column pairs
-                        if (i < rh && 2 * k + 1 < ow) in.pre[u] = ld1<SD>(det + R * dp + ws + C);
-                    } else if (band == 1) {   // LH
-                        if (2 * i + 1 < oh && k < rw) in.pre[u] = ld1<SD>(det + (hs + R) * dp + C);
-                    } else if (band == 2) {   // HH
-                        if (2 * i + 1 < oh && 2 * k + 1 < ow)
-                            in.pre[u] = ld1<SD>(det + (hs + R) * dp + ws + C);
-                    } else {                  // LL_L
-                        if (i < rh && k < rw) in.pre[u] = ld1<SL>(llp + R * lp + C);
-                    }
-                }
-                off += cnt;
-            }
-        }
-    }
-    // ---- level-1 details of this thread's block
-    {
-        const int64_t hs = ceil_shift(p.h, 1), ws = ceil_shift(p.w, 1);
-        const int64_t R = (r0 >> 1) + (lr0 >> 1), C = (c0 >> 1) + (lc0 >> 1);
-#pragma unroll
-        for (int i = 0; i < B1Y; ++i) {
-            if constexpr (FULL) {
-                ld_vec<SD, B1X>(det + (R + i) * dp + ws + C, in.hl1[i]);
-                ld_vec<SD, B1X>(det + (hs + R + i) * dp + C, in.lh1[i]);
-                ld_vec<SD, B1X>(det + (hs + R + i) * dp + ws + C, in.hh1[i]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < B1X; ++k) {
-                    const int lr = lr0 + 2 * i, lc = lc0 + 2 * k;
-                    const bool ok = lr < th && lc < tw;
-                    const bool r1 = ok && lr + 1 < th, c1 = ok && lc + 1 < tw;
-                    in.hl1[i][k] = c1 ? ld1<SD>(det + (R + i) * dp + ws + C + k) : 0.0f;
-                    in.lh1[i][k] = r1 ? ld1<SD>(det + (hs + R + i) * dp + C + k) : 0.0f;
-                    in.hh1[i][k] = (r1 && c1) ? ld1<SD>(det + (hs + R + i) * dp + ws + C + k) : 0.0f;
-                }
-            }
-        }
-    }
-    // ---- level-2 details (LL1 itself when L == 1, read into hl2's place: see body)
-    if (L >= 2) {
-        const int64_t hs = ceil_shift(p.h, 2), ws = ceil_shift(p.w, 2);
-        const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
-#pragma unroll
-        for (int i = 0; i < B2Y; ++i) {
-            if constexpr (FULL) {
-                ld_vec<SD, B2X>(det + (R + i) * dp + ws + C, in.hl2[i]);
-                ld_vec<SD, B2X>(det + (hs + R + i) * dp + C, in.lh2[i]);
-                ld_vec<SD, B2X>(det + (hs + R + i) * dp + ws + C, in.hh2[i]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < B2X; ++k) {
-                    const int lr = (lr0 >> 1) + 2 * i, lc = (lc0 >> 1) + 2 * k;
-                    const bool ok = lr < th1 && lc < tw1;
-                    const bool r1 = ok && lr + 1 < th1, c1 = ok && lc + 1 < tw1;
-                    in.hl2[i][k] = c1 ? ld1<SD>(det + (R + i) * dp + ws + C + k) : 0.0f;
-                    in.lh2[i][k] = r1 ? ld1<SD>(det + (hs + R + i) * dp + C + k) : 0.0f;
-                    in.hh2[i][k] = (r1 && c1) ? ld1<SD>(det + (hs + R + i) * dp + ws + C + k) : 0.0f;
-                }
-            }
-        }
-    }
-}
-
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
-__device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
-                                           const InvInT<SX, SD, SL, RY, RX, GY, GX>& in, float* sm) {
-    using G = Geo2D<SX, RY, RX, GY, GX>;
-    constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
-    constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
-
-    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
-    const int64_t r0 = ty * TH, c0 = tx * TW;
-    const int L = p.levels;
-    const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
-    const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
-    const int lr0 = rg * RY, lc0 = cg * RX;
-    const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
-    const int th2 = (th + 3) >> 2, tw2 = (tw + 3) >> 2;
-
-    const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
-    typename SX::raw* dst =
-        reinterpret_cast<typename SX::raw*>(p.dst) + item * p.dst_bstride + r0 * p.dst_pitch + c0;
-    const int64_t lp = p.ll_pitch;
-    const auto& hl1 = in.hl1;
-    const auto& lh1 = in.lh1;
-    const auto& hh1 = in.hh1;
-    const auto& hl2 = in.hl2;
-    const auto& lh2 = in.lh2;
-    const auto& hh2 = in.hh2;
-    const int nq = L >= 3 ? small_count<TH, TW>(L) : 0;
-    const auto& pre = in.pre;
-
-    // ---- levels L..3 in LDS from the prefetched values, producing the LL2
-    // region in buffer A (pitch TW/4) (edge tiles)
-    float* A = sm;
-    float* B = sm + G::AN;
-    float* D = sm + G::AN + G::BN;
-    if (!FULL && L >= 3) {
-#pragma unroll
-        for (int u = 0; u < G::QPT; ++u)
-            if (t + u * NT < nq) D[t + u * NT] = pre[u];
-        __syncthreads();
-        int off = 0;
-        int offs[6];
-        for (int lev = 3; lev <= L; ++lev) {
-            offs[lev] = off;
-            off += 3 * (TH >> lev) * (TW >> lev);
-        }
-        const float* Dll = D + off;
-        for (int lev = L; lev >= 3; --lev) {
-            const int rows = TH >> lev, cols = TW >> lev;
-            const int rh = (int)ceil_shift(th, lev), rw = (int)ceil_shift(tw, lev);
-            const int oh = (int)ceil_shift(th, lev - 1), ow = (int)ceil_shift(tw, lev - 1);
-            const float* lin = (lev & 1) ? B : A;     // output of level lev+1
-            float* out = (lev & 1) ? A : B;
-            const int pin = TW >> lev, pout = TW >> (lev - 1);
-            const float* Dh = D + offs[lev];
-            for (int b = t; b < rh * rw; b += NT) {
-                const int i = b / rw, k = b - i * rw;
-                const bool r1 = 2 * i + 1 < oh, c1 = 2 * k + 1 < ow;
-                const int e = i * cols + k;
-                const float ll = (lev == L) ? Dll[e] : lin[i * pin + k];
-                float x00, x01, x10, x11;
-                syn_edge(ll, Dh[e], Dh[rows * cols + e], Dh[2 * rows * cols + e], r1, c1, x00, x01,
-                         x10, x11);
-                const int o = (2 * i) * pout + 2 * k;
-                out[o] = x00;
-                if (c1) out[o + 1] = x01;
-                if (r1) out[o + pout] = x10;
-                if (r1 && c1) out[o + pout + 1] = x11;
-            }
-            __syncthreads();
-        }
-    }
-
-    // ---- LL2 of this thread (B2Y x B2X), or LL1 directly when L == 1
-    float ll1[B1Y][B1X];
-    if (L >= 2) {
-        float ll2[B2Y][B2X];
-        const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
-        if (FULL && L >= 3) {
-            // walk the ancestor path: LL_L -> ... -> LL3 (one 2x2 synthesis
-            // butterfly per level, keeping the child on the path), then the
-            // level-3 butterfly gives this thread's LL2 entries
-            const int64_t R3 = R >> 1, C3 = C >> 1;
-            float ll = in.walk[0];
-#pragma unroll
-            for (int jj = 2; jj >= 1; --jj) {
-                const int j = 3 + jj;               // level j -> level j-1 (j = 5, 4)
-                if (j <= L) {
-                    const int dy = (int)((R3 >> (j - 4)) & 1), dx = (int)((C3 >> (j - 4)) & 1);
-                    const float hl = in.walk[1 + 3 * jj], lh = in.walk[2 + 3 * jj],
-                                hh = in.walk[3 + 3 * jj];
-                    const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
-                    ll = 0.5f * (dx ? base + tt : base - tt);
-                }
-            }
-            const float hl = in.walk[1], lh = in.walk[2], hh = in.walk[3];   // level 3
-            const int dy = (int)(R & 1);
-#pragma unroll
-            for (int k = 0; k < B2X; ++k) {
-                const int dx = (int)((C + k) & 1);
-                const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
-                ll2[0][k] = 0.5f * (dx ? base + tt : base - tt);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < B2Y; ++i)
-#pragma unroll
-                for (int k = 0; k < B2X; ++k) {
-                    const int lr = (lr0 >> 2) + i, lc = (lc0 >> 2) + k;
-                    const bool ok = FULL || (lr < th2 && lc < tw2);
-                    if (L >= 3)
-                        ll2[i][k] = ok ? A[lr * (TW / 4) + lc] : 0.0f;
-                    else
-                        ll2[i][k] = ok ? ld1<SL>(llp + (R + i) * lp + C + k) : 0.0f;
-                }
-        }
-#pragma unroll
-        for (int i = 0; i < B2Y; ++i)
-#pragma unroll
-            for (int k = 0; k < B2X; ++k) {
-                const int lr = (lr0 >> 1) + 2 * i, lc = (lc0 >> 1) + 2 * k;
-                const bool r1 = FULL || lr + 1 < th1, c1 = FULL || lc + 1 < tw1;
-                syn_edge(ll2[i][k], hl2[i][k], lh2[i][k], hh2[i][k], r1, c1, ll1[2 * i][2 * k],
-                         ll1[2 * i][2 * k + 1], ll1[2 * i + 1][2 * k], ll1[2 * i + 1][2 * k + 1]);
-            }
-    } else {
-        const int64_t R = (r0 >> 1) + (lr0 >> 1), C = (c0 >> 1) + (lc0 >> 1);
-#pragma unroll
-        for (int i = 0; i < B1Y; ++i) {
-            if constexpr (FULL) {
-                ld_vec<SL, B1X>(llp + (R + i) * lp + C, ll1[i]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < B1X; ++k) {
-                    const bool ok = lr0 + 2 * i < th && lc0 + 2 * k < tw;
-                    ll1[i][k] = ok ? ld1<SL>(llp + (R + i) * lp + C + k) : 0.0f;
-                }
-            }
-        }
-    }
-
-    // ---- level 1 -> output block
-    float v[RY][RX];
-#pragma unroll
-    for (int i = 0; i < B1Y; ++i)
-#pragma unroll
-        for (int k = 0; k < B1X; ++k) {
-            const bool r1 = FULL || lr0 + 2 * i + 1 < th, c1 = FULL || lc0 + 2 * k + 1 < tw;
-            syn_edge(ll1[i][k], hl1[i][k], lh1[i][k], hh1[i][k], r1, c1, v[2 * i][2 * k],
-                     v[2 * i][2 * k + 1], v[2 * i + 1][2 * k], v[2 * i + 1][2 * k + 1]);
-        }
-    if constexpr (FULL) {
-#pragma unroll
-        for (int r = 0; r < RY; ++r) st_vec<SX, RX>(dst + (int64_t)(lr0 + r) * p.dst_pitch + lc0, v[r]);
-    } else {
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int c = 0; c < RX; ++c)
-                if (lr0 + r < th && lc0 + c < tw)
-                    st1<SX>(dst + (int64_t)(lr0 + r) * p.dst_pitch + lc0 + c, v[r][c]);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Kernels
-// ---------------------------------------------------------------------------
 #ifndef HAAR_MIN_WAVES_2D
 #define HAAR_MIN_WAVES_2D 1
 #endif

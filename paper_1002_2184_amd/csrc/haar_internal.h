@@ -8,6 +8,9 @@ namespace haar {
 
 inline int elem_bytes(int dtype) { return dtype == 0 ? 4 : 2; }
 
+// ceil(n / 2^j) on the host
+inline int64_t ceil_shift_host(int64_t n, int j) { return (n + ((int64_t)1 << j) - 1) >> j; }
+
 int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);
 int max_levels(int64_t n);

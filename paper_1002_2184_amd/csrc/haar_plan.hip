@@ -1,21 +1,622 @@
-// Batched plans (persistent work-list launches).
+// Batched transforms of uneven sizes: work-list plans and persistent kernels.
+//
+// A plan lists the work units of many items (2D: tiles, 1D: chunks), largest
+// items first, and one persistent kernel per execute drains the list: every
+// work-group claims the next unit with an atomic counter until the list is
+// exhausted.  The last work-group to leave resets the counters, so that the
+// next execute (or the next replay of a captured graph) starts from zero
+// without any memset.
+//
+// 1D items deeper than one chunk (levels > 12 with 4096-sample chunks):
+//   analysis  -- every chunk leaves its level-12 approximation in the item's
+//                output (the prefix that the deeper levels later overwrite);
+//                the last chunk of the item to finish (per-item counter,
+//                device-scope fences) computes the remaining levels of that
+//                prefix on chip;
+//   synthesis -- every chunk derives its own level-12 approximation by
+//                walking down its ancestor path from a_L (one synthesis
+//                butterfly per level), then runs its 12 on-chip levels.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
 #include "haar.h"
+#include "haar_1d_chunk.h"
+#include "haar_2d_tile.h"
 #include "haar_internal.h"
+
+namespace haar {
+
+struct PlanItem2D {
+    const void* in;
+    void* out;
+    int64_t h, w;
+    int32_t levels, vec_ok;
+};
+struct PlanTile2D {
+    int32_t item, ty, tx, full;
+};
+struct PlanItem1D {
+    const void* in;
+    void* out;
+    int64_t n;
+    int32_t levels;        // all levels of the item
+    int32_t chunk_levels;  // levels done inside one chunk: min(levels, 12)
+    int32_t nchunks;
+    int32_t vec_ok;
+};
+struct PlanChunk1D {
+    int32_t item, chunk;
+};
+
+constexpr int kPlanNT1 = 256, kPlanE1 = 16;              // 1D chunk: 4096 samples
+constexpr int kPlanC1 = kPlanNT1 * kPlanE1, kPlanLogC1 = 12;
+constexpr int kFinishMax = 1024;                          // on-chip finish: n / 4096 <= 1024
+
+// ---------------------------------------------------------------------------
+// Counters: ctr[0] = next work unit, ctr[1] = work-groups done,
+// ctr[2 + i] = finished chunks of 1D item i.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool claim(unsigned* ctr, unsigned* s_slot, unsigned total, unsigned& unit) {
+    if (threadIdx.x == 0) *s_slot = atomicAdd(&ctr[0], 1u);
+    __syncthreads();
+    unit = *s_slot;
+    __syncthreads();
+    return unit < total;
+}
+
+__device__ __forceinline__ void retire(unsigned* ctr) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&ctr[1], 1u) == gridDim.x - 1) {   // every work-group has left the loop
+            atomicExch(&ctr[0], 0u);
+            atomicExch(&ctr[1], 0u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D
+// ---------------------------------------------------------------------------
+template <class S, int GY, int GX, bool INV>
+__global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __restrict__ items,
+                                                        const PlanTile2D* __restrict__ tiles,
+                                                        unsigned ntiles, unsigned* ctr) {
+    constexpr int RX = 16 / S::kBytes;
+    using G = Geo2D<S, 4, RX, GY, GX>;
+    constexpr int SM_FWD = G::SMEM, SM_INV = G::AN + G::BN + G::QPT * G::NT;
+    __shared__ float sm[SM_FWD > SM_INV ? SM_FWD : SM_INV];
+    __shared__ unsigned s_slot;
+    unsigned unit;
+    while (claim(ctr, &s_slot, ntiles, unit)) {
+        const PlanTile2D d = tiles[unit];
+        const PlanItem2D it = items[d.item];
+        Pass2D p{};
+        p.h = it.h;
+        p.w = it.w;
+        p.batch = 1;
+        p.levels = it.levels;
+        p.vec_ok = it.vec_ok;
+        if (!INV) {
+            p.src = it.in;
+            p.det = it.out;
+            p.ll = it.out;
+            p.src_pitch = p.det_pitch = p.ll_pitch = it.w;
+        } else {
+            p.det = const_cast<void*>(it.in);
+            p.ll = const_cast<void*>(it.in);
+            p.dst = it.out;
+            p.det_pitch = p.ll_pitch = p.dst_pitch = it.w;
+        }
+        if (!INV) {
+            if (d.full) {
+                FwdIn<4, RX> in;
+                fwd2d_load<S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in);
+                fwd2d_body<S, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in, sm);
+            } else {
+                FwdIn<4, RX> in;
+                fwd2d_load<S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in);
+                fwd2d_body<S, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in, sm);
+            }
+        } else {
+            using In = InvInT<S, S, S, 4, RX, GY, GX>;
+            if (d.full) {
+                In in;
+                inv2d_load<S, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in);
+                inv2d_body<S, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in, sm);
+            } else {
+                In in;
+                inv2d_load<S, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in);
+                inv2d_body<S, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in, sm);
+            }
+        }
+        __syncthreads();   // LDS reuse by the next unit
+    }
+    retire(ctr);
+}
+
+// ---------------------------------------------------------------------------
+// 1D
+// ---------------------------------------------------------------------------
+// The remaining levels of a deep item on its prefix y[0, n12) (the chunks'
+// level-12 approximations), in place, by one work-group.
+template <class S>
+__device__ void finish1d(const PlanItem1D& it, df* buf0, df* buf1) {
+    using raw = typename S::raw;
+    raw* y = reinterpret_cast<raw*>(it.out);
+    const int t = threadIdx.x;
+    const int64_t n12 = ceil_shift(it.n, kPlanLogC1);
+    const int lr = it.levels - kPlanLogC1;
+    for (int64_t i = t; i < n12; i += blockDim.x) buf0[i] = df_from(ld1<S>(y + i));
+    __syncthreads();
+    df* a = buf0;
+    df* b = buf1;
+    int64_t len = n12;
+    for (int lev = 1; lev <= lr; ++lev) {
+        const int64_t half = len >> 1, na = len - half;
+        const int64_t ns = ceil_shift(n12, lev);     // == na: offset of this level's details
+        for (int64_t P = t; P < na; P += blockDim.x) {
+            if (P < half) {
+                st1<S>(y + ns + P, f_norm(df_diff(a[2 * P + 1], a[2 * P]), lev));
+                b[P] = df_add(a[2 * P], a[2 * P + 1]);
+            } else {
+                b[P] = df_s2(a[2 * P]);             // carried sample
+            }
+        }
+        __syncthreads();
+        df* tmp = a;
+        a = b;
+        b = tmp;
+        len = na;
+    }
+    for (int64_t P = t; P < len; P += blockDim.x) st1<S>(y + P, df_norm(a[P], lr));
+}
+
+template <class S, bool INV>
+__global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __restrict__ items,
+                                                         const PlanChunk1D* __restrict__ chunks,
+                                                         unsigned nunits, unsigned* ctr) {
+    constexpr int NW = kPlanNT1 / 64;
+    __shared__ df smd[NW];
+    __shared__ float smf[NW * 8];
+    __shared__ df fin0[INV ? 1 : kFinishMax];
+    __shared__ df fin1[INV ? 1 : kFinishMax];
+    __shared__ unsigned s_slot, s_last;
+    unsigned unit;
+    while (claim(ctr, &s_slot, nunits, unit)) {
+        const PlanChunk1D d = chunks[unit];
+        const PlanItem1D it = items[d.item];
+        Pass1D p{};
+        p.n = it.n;
+        p.batch = 1;
+        p.levels = it.chunk_levels;
+        p.vec_ok = it.vec_ok;
+        const bool full = it.vec_ok && (int64_t)(d.chunk + 1) * kPlanC1 <= it.n;
+        if (!INV) {
+            p.src = it.in;
+            p.det = it.out;
+            p.ll = it.out;
+            if (full)
+                fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd);
+            else
+                fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd);
+            if (it.levels > it.chunk_levels) {
+                __threadfence();            // this chunk's level-12 value, device-wide
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    s_last = atomicAdd(&ctr[2 + d.item], 1u) == (unsigned)(it.nchunks - 1);
+                __syncthreads();
+                if (s_last) {
+                    __threadfence();        // see the other chunks' values
+                    finish1d<S>(it, fin0, fin1);
+                    if (threadIdx.x == 0) atomicExch(&ctr[2 + d.item], 0u);
+                }
+            }
+        } else {
+            p.det = const_cast<void*>(it.in);
+            p.ll = const_cast<void*>(it.in);
+            p.dst = it.out;
+            bool has_top = false;
+            float top = 0.0f;
+            if (it.levels > it.chunk_levels) {
+                // a_12[chunk] from a_L down the ancestor path (all loads first)
+                using raw = typename S::raw;
+                const raw* y = reinterpret_cast<const raw*>(it.in);
+                const int L = it.levels;
+                const int64_t c = d.chunk;
+                float dv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int j = L - q;                    // detail level
+                    dv[q] = 0.0f;
+                    if (j > kPlanLogC1) {
+                        const int64_t P = c >> (j - kPlanLogC1);
+                        const int64_t len = ceil_shift(it.n, j - 1);
+                        if (2 * P + 1 < len) dv[q] = ld1<S>(y + ceil_shift(it.n, j) + P);
+                    }
+                }
+                float a = ld1<S>(y + (c >> (L - kPlanLogC1)));
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int j = L - q;
+                    if (j > kPlanLogC1) {
+                        const int64_t k = c >> (j - 1 - kPlanLogC1);   // index at level j-1
+                        const int64_t P = k >> 1;
+                        const int64_t len = ceil_shift(it.n, j - 1);
+                        if (2 * P + 1 < len) a = (k & 1) ? (a + dv[q]) * kRs2Hi : (a - dv[q]) * kRs2Hi;
+                    }
+                }
+                has_top = true;
+                top = a;
+            }
+            if (full)
+                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smf, has_top, top);
+            else
+                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smf, has_top, top);
+        }
+        __syncthreads();
+    }
+    retire(ctr);
+}
+
+}  // namespace haar
 
 using namespace haar;
 
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct haar_plan {
+    int dim = 0;
+    int dtype = 0;
+    int inverse = 0;
+    int cfg = 1;                       // 2D tile configuration (0: 32 rows x 16 vectors, 1: x 32)
+    std::vector<PlanItem2D> items2;
+    std::vector<PlanTile2D> tiles2[2];  // per tile configuration
+    std::vector<PlanItem1D> items1;
+    std::vector<PlanChunk1D> chunks1;
+    size_t off_items = 0, off_units = 0, ws_bytes = 0;
+    int64_t nunits = 0;
+    int grid = 0;
+    bool uploaded = false;
+    const void* uploaded_to = nullptr;
+};
+
+namespace {
+
+constexpr int kPlanCfgs2D = 2;          // tile configurations with plan kernels: 0 and 1
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool overlap(const void* a, const void* b, uint64_t bytes) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+template <class K>
+int grid_for(K kernel, int threads) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu * device_cus();
+}
+
+// launch helpers -------------------------------------------------------------
+template <class S>
+hipError_t launch_plan2d(const haar_plan* pl, void* ws, hipStream_t s, bool query_only, int* grid) {
+    const PlanItem2D* items = (const PlanItem2D*)((char*)ws + pl->off_items);
+    const PlanTile2D* tiles = (const PlanTile2D*)((char*)ws + pl->off_units);
+    unsigned* ctr = (unsigned*)ws;
+    const unsigned n = (unsigned)pl->nunits;
+    auto go = [&](auto kernel, int threads) -> hipError_t {
+        const int g = std::min<int64_t>(grid_for(kernel, threads), std::max<int64_t>(1, n));
+        if (grid) *grid = g;
+        if (query_only) return hipSuccess;
+        hipLaunchKernelGGL(kernel, dim3(g), dim3(threads), 0, s, items, tiles, n, ctr);
+        return hipGetLastError();
+    };
+    if (pl->cfg == 0)
+        return pl->inverse ? go(plan2d_kernel<S, 8, 32, true>, 256) : go(plan2d_kernel<S, 8, 32, false>, 256);
+    return pl->inverse ? go(plan2d_kernel<S, 8, 64, true>, 512) : go(plan2d_kernel<S, 8, 64, false>, 512);
+}
+
+template <class S>
+hipError_t launch_plan1d(const haar_plan* pl, void* ws, hipStream_t s, bool query_only, int* grid) {
+    const PlanItem1D* items = (const PlanItem1D*)((char*)ws + pl->off_items);
+    const PlanChunk1D* chunks = (const PlanChunk1D*)((char*)ws + pl->off_units);
+    unsigned* ctr = (unsigned*)ws;
+    const unsigned n = (unsigned)pl->nunits;
+    auto go = [&](auto kernel) -> hipError_t {
+        const int g = std::min<int64_t>(grid_for(kernel, kPlanNT1), std::max<int64_t>(1, n));
+        if (grid) *grid = g;
+        if (query_only) return hipSuccess;
+        hipLaunchKernelGGL(kernel, dim3(g), dim3(kPlanNT1), 0, s, items, chunks, n, ctr);
+        return hipGetLastError();
+    };
+    return pl->inverse ? go(plan1d_kernel<S, true>) : go(plan1d_kernel<S, false>);
+}
+
+hipError_t launch_plan(const haar_plan* pl, void* ws, hipStream_t s, bool query_only, int* grid) {
+    if (pl->dim == 2) {
+        switch (pl->dtype) {
+            case 0: return launch_plan2d<StF32>(pl, ws, s, query_only, grid);
+            case 1: return launch_plan2d<StBF16>(pl, ws, s, query_only, grid);
+            default: return launch_plan2d<StF16>(pl, ws, s, query_only, grid);
+        }
+    }
+    switch (pl->dtype) {
+        case 0: return launch_plan1d<StF32>(pl, ws, s, query_only, grid);
+        case 1: return launch_plan1d<StBF16>(pl, ws, s, query_only, grid);
+        default: return launch_plan1d<StF16>(pl, ws, s, query_only, grid);
+    }
+}
+
+void layout(haar_plan* pl, size_t item_bytes, size_t nitems, size_t unit_bytes, int64_t nunits,
+            size_t counters) {
+    pl->off_items = align256(counters * sizeof(unsigned));
+    pl->off_units = align256(pl->off_items + item_bytes * nitems);
+    pl->ws_bytes = align256(pl->off_units + unit_bytes * (size_t)nunits);
+    pl->nunits = nunits;
+}
+
+}  // namespace
+
 extern "C" {
-int haar_plan_create_1d(const haar_item_1d*, int64_t, int32_t, int32_t, haar_plan** out) {
-    if (out) *out = nullptr;
-    return set_error(HAAR_ERR_UNSUPPORTED, "plans not built yet");
+
+int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype, int32_t inverse,
+                        haar_plan** out) {
+    if (!out) return set_error(HAAR_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    if (dtype < 0 || dtype > 2) return set_error(HAAR_ERR_DTYPE, "dtype %d is not a haar_dtype", dtype);
+    if (count < 1) return set_error(HAAR_ERR_PLAN, "a plan needs at least one item");
+    if (!items) return set_error(HAAR_ERR_NULL, "items is NULL");
+    const int eb = elem_bytes(dtype);
+    for (int64_t i = 0; i < count; ++i) {
+        const haar_item_2d& it = items[i];
+        if (!it.in || !it.out) return set_error(HAAR_ERR_NULL, "item %lld: NULL pointer", (long long)i);
+        if (it.height < 1 || it.width < 1 || it.height > (1 << 30) || it.width > (1 << 30))
+            return set_error(HAAR_ERR_SHAPE, "item %lld: bad shape", (long long)i);
+        const int maxl = std::min(kMaxPassLevels2D, max_levels(std::max(it.height, it.width)));
+        if (it.levels < 1 || it.levels > maxl)
+            return set_error(HAAR_ERR_LEVELS, "item %lld: levels %d outside [1, %d]", (long long)i,
+                             it.levels, maxl);
+        if (overlap(it.in, it.out, (uint64_t)(it.height * it.width * eb)))
+            return set_error(HAAR_ERR_ALIAS, "item %lld: input and output overlap", (long long)i);
+    }
+    haar_plan* pl = new haar_plan();
+    pl->dim = 2;
+    pl->dtype = dtype;
+    pl->inverse = inverse ? 1 : 0;
+    // largest items first
+    std::vector<int64_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        return items[a].height * items[a].width > items[b].height * items[b].width;
+    });
+    for (int64_t oi = 0; oi < count; ++oi) {
+        const haar_item_2d& it = items[order[oi]];
+        PlanItem2D pi{};
+        pi.in = it.in;
+        pi.out = it.out;
+        pi.h = it.height;
+        pi.w = it.width;
+        pi.levels = it.levels;
+        // vector path: 16-byte rows and aligned level-1/2 band origins
+        const int rx = 16 / eb;
+        const int64_t b1x = rx / 2, b2x = rx / 4;
+        const void* region = inverse ? it.out : it.in;
+        const void* coef = inverse ? it.in : it.out;
+        bool ok = aligned(region, 16) && aligned(coef, 16) && (it.width * eb) % 16 == 0;
+        ok = ok && it.width % b1x == 0 && ((it.width + 1) / 2) % b1x == 0 && ((it.width + 3) / 4) % b2x == 0;
+        pi.vec_ok = ok ? 1 : 0;
+        pl->items2.push_back(pi);
+        for (int c = 0; c < kPlanCfgs2D; ++c) {
+            const Tile2D tc = tile_config_2d(eb, c);
+            const int64_t tx = (it.width + tc.tw() - 1) / tc.tw(), ty = (it.height + tc.th() - 1) / tc.th();
+            for (int64_t y = 0; y < ty; ++y)
+                for (int64_t x = 0; x < tx; ++x) {
+                    const bool full = ok && (y + 1) * tc.th() <= it.height && (x + 1) * tc.tw() <= it.width;
+                    pl->tiles2[c].push_back(PlanTile2D{(int32_t)oi, (int32_t)y, (int32_t)x, full ? 1 : 0});
+                }
+        }
+    }
+    if (pl->tiles2[0].size() >= (1u << 31)) {
+        delete pl;
+        return set_error(HAAR_ERR_SHAPE, "plan has too many tiles");
+    }
+    const int c = choose_config_2d(dtype, inverse != 0, items[order[0]].height, items[order[0]].width,
+                                   items[order[0]].levels);
+    pl->cfg = tile_config_2d(eb, c).gx == 32 ? 0 : 1;
+    layout(pl, sizeof(PlanItem2D), pl->items2.size(), sizeof(PlanTile2D),
+           (int64_t)std::max(pl->tiles2[0].size(), pl->tiles2[1].size()), 2);
+    pl->nunits = (int64_t)pl->tiles2[pl->cfg].size();
+    *out = pl;
+    return HAAR_OK;
 }
-int haar_plan_create_2d(const haar_item_2d*, int64_t, int32_t, int32_t, haar_plan** out) {
-    if (out) *out = nullptr;
-    return set_error(HAAR_ERR_UNSUPPORTED, "plans not built yet");
+
+int haar_plan_create_1d(const haar_item_1d* items, int64_t count, int32_t dtype, int32_t inverse,
+                        haar_plan** out) {
+    if (!out) return set_error(HAAR_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    if (dtype < 0 || dtype > 2) return set_error(HAAR_ERR_DTYPE, "dtype %d is not a haar_dtype", dtype);
+    if (count < 1) return set_error(HAAR_ERR_PLAN, "a plan needs at least one item");
+    if (!items) return set_error(HAAR_ERR_NULL, "items is NULL");
+    const int eb = elem_bytes(dtype);
+    int64_t total_chunks = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const haar_item_1d& it = items[i];
+        if (!it.in || !it.out) return set_error(HAAR_ERR_NULL, "item %lld: NULL pointer", (long long)i);
+        if (it.length < 1 || it.length > ((int64_t)1 << 40))
+            return set_error(HAAR_ERR_SHAPE, "item %lld: bad length", (long long)i);
+        const int maxl = max_levels(it.length);
+        if (it.levels < 1 || it.levels > maxl)
+            return set_error(HAAR_ERR_LEVELS, "item %lld: levels %d outside [1, %d]", (long long)i,
+                             it.levels, maxl);
+        if (it.levels > kPlanLogC1 && ceil_shift_host(it.length, kPlanLogC1) > kFinishMax)
+            return set_error(HAAR_ERR_UNSUPPORTED,
+                             "item %lld: more than 12 levels on more than %d x 4096 samples in a plan",
+                             (long long)i, kFinishMax);
+        if (it.levels > kPlanLogC1 + 8)
+            return set_error(HAAR_ERR_UNSUPPORTED, "item %lld: more than 20 levels in a plan", (long long)i);
+        if (overlap(it.in, it.out, (uint64_t)(it.length * eb)))
+            return set_error(HAAR_ERR_ALIAS, "item %lld: input and output overlap", (long long)i);
+        total_chunks += (it.length + kPlanC1 - 1) / kPlanC1;
+    }
+    if (total_chunks >= (1ll << 31) || count >= (1ll << 30))
+        return set_error(HAAR_ERR_SHAPE, "plan has too many chunks");
+    haar_plan* pl = new haar_plan();
+    pl->dim = 1;
+    pl->dtype = dtype;
+    pl->inverse = inverse ? 1 : 0;
+    std::vector<int64_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return items[a].length > items[b].length; });
+    for (int64_t oi = 0; oi < count; ++oi) {
+        const haar_item_1d& it = items[order[oi]];
+        PlanItem1D pi{};
+        pi.in = it.in;
+        pi.out = it.out;
+        pi.n = it.length;
+        pi.levels = it.levels;
+        pi.chunk_levels = std::min(it.levels, kPlanLogC1);
+        pi.nchunks = (int32_t)((it.length + kPlanC1 - 1) / kPlanC1);
+        const void* region = inverse ? it.out : it.in;
+        bool ok = aligned(region, 16) && aligned(it.in, 16) && aligned(it.out, 16);
+        for (int lev = 1; lev <= 4 && lev <= pi.chunk_levels; ++lev) {
+            const int cnt = kPlanE1 >> lev;
+            const int v = cnt < 16 / eb ? cnt : 16 / eb;
+            ok = ok && ceil_shift_host(it.length, lev) % v == 0;
+        }
+        pi.vec_ok = ok ? 1 : 0;
+        pl->items1.push_back(pi);
+        for (int32_t c = 0; c < pi.nchunks; ++c) pl->chunks1.push_back(PlanChunk1D{(int32_t)oi, c});
+    }
+    layout(pl, sizeof(PlanItem1D), pl->items1.size(), sizeof(PlanChunk1D), (int64_t)pl->chunks1.size(),
+           2 + (size_t)count);
+    *out = pl;
+    return HAAR_OK;
 }
-int haar_plan_workspace_size(const haar_plan*, size_t*) { return set_error(HAAR_ERR_PLAN, "no plan"); }
-int haar_plan_upload(haar_plan*, void*, void*) { return set_error(HAAR_ERR_PLAN, "no plan"); }
-int haar_plan_execute(const haar_plan*, void*, void*) { return set_error(HAAR_ERR_PLAN, "no plan"); }
-int haar_plan_info(const haar_plan*, int64_t*, int32_t*) { return set_error(HAAR_ERR_PLAN, "no plan"); }
-int haar_plan_destroy(haar_plan*) { return HAAR_OK; }
+
+int haar_plan_workspace_size(const haar_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return set_error(HAAR_ERR_NULL, "plan or bytes is NULL");
+    *bytes = plan->ws_bytes;
+    return HAAR_OK;
 }
+
+int haar_plan_upload(haar_plan* plan, void* workspace, void* stream) {
+    if (!plan) return set_error(HAAR_ERR_PLAN, "plan is NULL");
+    if (!workspace || !aligned(workspace, 256))
+        return set_error(HAAR_ERR_WORKSPACE, "workspace is NULL or not 256-byte aligned");
+    if (int rc = fault_injected(); rc != HAAR_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    hipError_t e = hipMemsetAsync(ws, 0, plan->off_items, s);
+    if (e != hipSuccess) return hip_error(e, "hipMemsetAsync (plan counters)");
+    const void* it = plan->dim == 2 ? (const void*)plan->items2.data() : (const void*)plan->items1.data();
+    const size_t itb = plan->dim == 2 ? plan->items2.size() * sizeof(PlanItem2D)
+                                      : plan->items1.size() * sizeof(PlanItem1D);
+    e = hipMemcpyAsync(ws + plan->off_items, it, itb, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync (plan items)");
+    if (plan->dim == 2) {
+        e = hipMemcpyAsync(ws + plan->off_units, plan->tiles2[plan->cfg].data(),
+                           plan->tiles2[plan->cfg].size() * sizeof(PlanTile2D), hipMemcpyHostToDevice, s);
+    } else {
+        e = hipMemcpyAsync(ws + plan->off_units, plan->chunks1.data(),
+                           plan->chunks1.size() * sizeof(PlanChunk1D), hipMemcpyHostToDevice, s);
+    }
+    if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync (plan work-list)");
+    plan->uploaded = true;
+    plan->uploaded_to = workspace;
+    return HAAR_OK;
+}
+
+int haar_plan_execute(const haar_plan* plan, void* workspace, void* stream) {
+    if (!plan) return set_error(HAAR_ERR_PLAN, "plan is NULL");
+    if (!workspace) return set_error(HAAR_ERR_WORKSPACE, "workspace is NULL");
+    if (!plan->uploaded || plan->uploaded_to != workspace)
+        return set_error(HAAR_ERR_PLAN, "plan was not uploaded to this workspace");
+    if (int rc = fault_injected(); rc != HAAR_OK) return rc;
+    hipError_t e = launch_plan(plan, workspace, (hipStream_t)stream, false, nullptr);
+    return e == hipSuccess ? HAAR_OK : hip_error(e, "plan launch");
+}
+
+int haar_plan_info(const haar_plan* plan, int64_t* tiles, int32_t* grid) {
+    if (!plan) return set_error(HAAR_ERR_PLAN, "plan is NULL");
+    if (tiles) *tiles = plan->nunits;
+    if (grid) {
+        int g = 0;
+        hipError_t e = launch_plan(plan, nullptr, nullptr, true, &g);
+        if (e != hipSuccess) return hip_error(e, "occupancy query");
+        *grid = g;
+    }
+    return HAAR_OK;
+}
+
+int haar_plan_set_config(haar_plan* plan, int32_t config) {
+    if (!plan) return set_error(HAAR_ERR_PLAN, "plan is NULL");
+    if (plan->dim != 2) return config == 0 ? HAAR_OK : set_error(HAAR_ERR_UNSUPPORTED, "1D plans have one chunk shape");
+    if (config < 0 || config >= kPlanCfgs2D)
+        return set_error(HAAR_ERR_UNSUPPORTED, "plan tile configuration %d not available", config);
+    plan->cfg = config;
+    plan->nunits = (int64_t)plan->tiles2[config].size();
+    plan->uploaded = false;          // the work-list changed: upload again
+    plan->uploaded_to = nullptr;
+    return HAAR_OK;
+}
+
+int haar_plan_tune(haar_plan* plan, void* workspace, void* stream, int32_t* choice) {
+    if (!plan) return set_error(HAAR_ERR_PLAN, "plan is NULL");
+    if (!workspace || !choice) return set_error(HAAR_ERR_NULL, "workspace or choice is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int ncfg = plan->dim == 2 ? kPlanCfgs2D : 1;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return set_error(HAAR_ERR_HIP, "hipEventCreate");
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return set_error(HAAR_ERR_HIP, "hipEventCreate");
+    }
+    int best = plan->cfg, rc = HAAR_OK;
+    float best_ms = 1e30f;
+    for (int c = 0; c < ncfg && rc == HAAR_OK; ++c) {
+        if ((rc = haar_plan_set_config(plan, c)) != HAAR_OK) break;
+        if ((rc = haar_plan_upload(plan, workspace, stream)) != HAAR_OK) break;
+        for (int i = 0; i < 2 && rc == HAAR_OK; ++i) rc = haar_plan_execute(plan, workspace, stream);
+        std::vector<float> ts;
+        for (int i = 0; i < 5 && rc == HAAR_OK; ++i) {
+            (void)hipEventRecord(a, s);
+            rc = haar_plan_execute(plan, workspace, stream);
+            (void)hipEventRecord(b, s);
+            if (hipEventSynchronize(b) != hipSuccess) rc = set_error(HAAR_ERR_HIP, "hipEventSynchronize");
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            ts.push_back(ms);
+        }
+        if (rc == HAAR_OK) {
+            std::sort(ts.begin(), ts.end());
+            if (ts[ts.size() / 2] < best_ms) {
+                best_ms = ts[ts.size() / 2];
+                best = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != HAAR_OK) return rc;
+    if ((rc = haar_plan_set_config(plan, best)) != HAAR_OK) return rc;
+    if ((rc = haar_plan_upload(plan, workspace, stream)) != HAAR_OK) return rc;
+    *choice = best;
+    return HAAR_OK;
+}
+
+int haar_plan_destroy(haar_plan* plan) {
+    delete plan;
+    return HAAR_OK;
+}
+
+}  // extern "C"

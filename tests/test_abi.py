@@ -137,3 +137,50 @@ def test_tuning_validation(abi):
     assert "tile" in abi.haar_tune_candidate_name(0, 0)
     assert abi.haar_force_config_2d(0, 99) == 9
     assert abi.haar_force_config_2d(0, -1) == 0
+
+
+def _items2d(abi, shapes, levels):
+    items = (abi.Item2D * len(shapes))()
+    for i, (h, w) in enumerate(shapes):
+        items[i] = abi.Item2D(X + i * (1 << 24), Y + i * (1 << 24), h, w, levels)
+    return items
+
+
+def test_plan_validation_and_sizes(abi, monkeypatch):
+    plan = ctypes.c_void_p()
+    items = _items2d(abi, [(64, 96), (33, 300)], 3)
+    assert abi.haar_plan_create_2d(items, 2, 0, 0, ctypes.byref(plan)) == 0
+    nb = ctypes.c_size_t()
+    assert abi.haar_plan_workspace_size(plan, ctypes.byref(nb)) == 0
+    assert nb.value % 256 == 0 and nb.value > 0
+    tiles = ctypes.c_int64()
+    assert abi.haar_plan_info(plan, ctypes.byref(tiles), None) == 0
+    # 32x256 f32 tiles: 64x96 -> 2x1, 33x300 -> 2x2
+    assert tiles.value == 6
+    assert abi.haar_plan_execute(plan, X, 0) == 8          # not uploaded
+    assert abi.haar_plan_set_config(plan, 5) == 9
+    monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")
+    assert abi.haar_plan_upload(plan, X, 0) == 7             # stopped before any HIP call
+    assert abi.haar_plan_upload(plan, X + 8, 0) == 6         # misaligned workspace
+    assert abi.haar_plan_destroy(plan) == 0
+    bad = _items2d(abi, [(64, 96)], 6)                       # > 5 levels in a 2D plan
+    assert abi.haar_plan_create_2d(bad, 1, 0, 0, ctypes.byref(plan)) == 4
+    alias = (abi.Item2D * 1)(abi.Item2D(X, X + 4, 8, 8, 1))
+    assert abi.haar_plan_create_2d(alias, 1, 0, 0, ctypes.byref(plan)) == 5
+    assert abi.haar_plan_create_2d(items, 0, 0, 0, ctypes.byref(plan)) == 8
+    assert abi.haar_plan_create_2d(items, 2, 4, 0, ctypes.byref(plan)) == 2
+
+
+def test_plan_1d_validation(abi):
+    plan = ctypes.c_void_p()
+    items = (abi.Item1D * 3)(abi.Item1D(X, Y, 4096, 12), abi.Item1D(X + (1 << 26), Y + (1 << 26), 1 << 20, 20),
+                             abi.Item1D(X + (2 << 26), Y + (2 << 26), 1000, 10))
+    assert abi.haar_plan_create_1d(items, 3, 0, 0, ctypes.byref(plan)) == 0
+    tiles = ctypes.c_int64()
+    assert abi.haar_plan_info(plan, ctypes.byref(tiles), None) == 0
+    assert tiles.value == 1 + 256 + 1
+    assert abi.haar_plan_destroy(plan) == 0
+    deep = (abi.Item1D * 1)(abi.Item1D(X, Y + (1 << 40), 1 << 23, 23))
+    assert abi.haar_plan_create_1d(deep, 1, 0, 0, ctypes.byref(plan)) == 9
+    bad = (abi.Item1D * 1)(abi.Item1D(X, Y, 100, 8))
+    assert abi.haar_plan_create_1d(bad, 1, 0, 0, ctypes.byref(plan)) == 4
