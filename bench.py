@@ -139,6 +139,136 @@ def write_traffic(fetch_csv: str, write_csv: str, command: str):
     print(json.dumps(doc))
 
 
+def _timed(fn, reps, warm, stream):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def suite():
+    """The other workloads, each beside the plain FP32 transform on this GPU.
+    Prints one JSON line per workload (not the benchmark contract line)."""
+    import numpy as np
+    import torch
+
+    from paper_1002_2184_amd import autograd as AG
+    from paper_1002_2184_amd import plan as PL
+    from paper_1002_2184_amd import transform as T
+    from workloads import generators as G
+
+    dev = torch.device("cuda", 0)
+    st = torch.cuda.current_stream(dev)
+
+    # 1) one 65536-sample FP32 signal, 16 levels: latency of fwd + inv
+    x = torch.from_numpy(G.config1()).to(dev)
+    y, z = torch.empty_like(x), torch.empty_like(x)
+
+    def one():
+        T.fwd1d(x, 16, out=y)
+        T.inv1d(y, 16, out=z)
+    ms = _timed(one, 200, 20, st)
+    g = torch.cuda.CUDAGraph()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(st)
+    with torch.cuda.stream(s2):
+        one()
+        with torch.cuda.graph(g, stream=s2):
+            one()
+    st.wait_stream(s2)
+    torch.cuda.synchronize()
+    msg = _timed(g.replay, 200, 20, st)
+    print(json.dumps({"workload": "1d-white-65536-L16 fwd+inv", "us_eager": round(ms * 1e3, 2),
+                      "us_graph": round(msg * 1e3, 2),
+                      "gbps_eager": round(4 * 65536 * 4 / (ms * 1e-3) / 1e9, 1),
+                      "note": "latency-bound: 1 MiB moved per fwd+inv"}), flush=True)
+
+    # 2) 1024 uneven signals 2^10..2^20, full depth: one persistent launch
+    sigs = G.config3()
+    levels = [int(np.log2(v.size)) for v in sigs]
+    xs = [torch.from_numpy(v).to(dev) for v in sigs]
+    ys = [torch.empty_like(v) for v in xs]
+    total = sum(v.numel() for v in xs)
+    plan = PL.Plan1D(xs, ys, levels)
+    ms_plan = _timed(plan.execute, 20, 3, st)
+
+    def loop():
+        for v, w, lv in zip(xs, ys, levels):
+            T.fwd1d(v, lv, out=w)
+    ms_loop = _timed(loop, 3, 1, st)
+    flat = torch.cat([v.view(-1) for v in xs])[: (total // 65536) * 65536].view(-1, 65536)
+    flat_y = torch.empty_like(flat)
+    ms_plain = _timed(lambda: T.fwd1d(flat, 16, out=flat_y), 20, 3, st)
+    print(json.dumps({"workload": "1d-batched-uneven-1024x2^[10,20]-fulldepth fwd",
+                      "elements": int(total), "ms_plan": round(ms_plan, 4),
+                      "gbps_plan": round(2 * total * 4 / (ms_plan * 1e-3) / 1e9, 1),
+                      "ms_per_signal_loop": round(ms_loop, 3),
+                      "gbps_plain_same_bytes_65536x16": round(2 * flat.numel() * 4 / (ms_plain * 1e-3) / 1e9, 1)}),
+          flush=True)
+    del xs, ys, plan, flat, flat_y
+    torch.cuda.empty_cache()
+
+    # 3) autograd 64x3x512x512, 3 levels: fwd + bwd vs plain fwd + inv
+    xa = torch.from_numpy(G.config4()).to(dev).requires_grad_(True)
+    ga = torch.randn_like(xa)
+    ya, za = torch.empty_like(xa), torch.empty_like(xa)
+    n4 = xa.numel()
+
+    def ag():
+        out = AG.HaarFwd2D.apply(xa, 3)
+        torch.autograd.grad(out, xa, ga)
+    ms_ag = _timed(ag, 20, 3, st)
+    xd = xa.detach()
+
+    def plain():
+        T.fwd2d(xd, 3, out=ya)
+        T.inv2d(ya, 3, out=za)
+    ms_pl = _timed(plain, 20, 3, st)
+    print(json.dumps({"workload": "2d-autograd-64x3x512x512-L3 fwd+bwd",
+                      "gbps_fwd_bwd": round(4 * n4 * 4 / (ms_ag * 1e-3) / 1e9, 1),
+                      "gbps_plain_fwd_inv": round(4 * n4 * 4 / (ms_pl * 1e-3) / 1e9, 1),
+                      "ms_fwd_bwd": round(ms_ag, 4), "ms_plain": round(ms_pl, 4)}), flush=True)
+    del xa, ga, ya, za, xd
+    torch.cuda.empty_cache()
+
+    # 4) 512 BF16 images, even H, W in [256, 2048], 4 levels: fwd + bwd plans,
+    #    and the same images in FP32 through the same path
+    imgs, grads = G.config5()
+    res = {"workload": "2d-batched-bf16-512-uneven-L4 fwd+bwd"}
+    for name, dt in (("bf16", torch.bfloat16), ("f32", torch.float32)):
+        if dt == torch.bfloat16:
+            xs = [torch.from_numpy(a.view(np.int16)).to(dev).view(torch.bfloat16) for a in imgs]
+            gs = [torch.from_numpy(a.view(np.int16)).to(dev).view(torch.bfloat16) for a in grads]
+        else:
+            xs = [torch.from_numpy(G.bf16_bits_to_f32(a)).to(dev) for a in imgs]
+            gs = [torch.from_numpy(G.bf16_bits_to_f32(a)).to(dev) for a in grads]
+        ys = [torch.empty_like(v) for v in xs]
+        zs = [torch.empty_like(v) for v in gs]
+        pf = PL.Plan2D(xs, ys, 4)
+        pb = PL.Plan2D(gs, zs, 4, inverse=True)
+
+        def fb():
+            pf.execute()
+            pb.execute()
+        ms5 = _timed(fb, 10, 2, st)
+        nel = sum(v.numel() for v in xs)
+        res[f"ms_{name}"] = round(ms5, 4)
+        res[f"gbps_{name}"] = round(4 * nel * xs[0].element_size() / (ms5 * 1e-3) / 1e9, 1)
+        res[f"elements_per_s_{name}"] = round(2 * nel / (ms5 * 1e-3) / 1e9, 2)
+        del xs, gs, ys, zs, pf, pb
+        torch.cuda.empty_cache()
+    res["unit_elements_per_s"] = "G elements/s, fwd + bwd"
+    print(json.dumps(res), flush=True)
+
+
 def cpu_baseline(x_np, budget_s: float):
     """The FP64 oracle (fwd + inv of the same image) on this host's cores."""
     import numpy as np
@@ -170,7 +300,12 @@ def main():
                     help="run the dispatches profiled by the rocprofv3 counter passes and exit")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="summarise two rocprofv3 counter CSVs into the profiles/ traffic file")
+    ap.add_argument("--suite", action="store_true",
+                    help="measure the other workloads (1D latency, batched, autograd, BF16) and exit")
     args = ap.parse_args()
+    if args.suite:
+        suite()
+        return
     if args.write_traffic:
         write_traffic(*args.write_traffic)
         return

@@ -275,7 +275,8 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
     } else if (L > LOG_E) {
         const int st = L - LOG_E;
         const int P = t >> st;
-        if ((lane & ((1 << st) - 1)) == 0 && P < ceil_shift(cl, L)) v = ld1<SL>(llp + (c0 >> L) + P);
+        if ((lane & ((1 << st) - 1)) == 0 && P < ceil_shift(cl, L))
+            v = has_top ? top : ld1<SL>(llp + (c0 >> L) + P);
     }
 
     // ---- wavefront levels, from the deepest down
@@ -338,6 +339,77 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
         for (int e = 0; e < E; ++e)
             if (t * E + e < cl) st1<SX>(dst + t * E + e, a[e]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Deep transforms without scratch
+// ---------------------------------------------------------------------------
+constexpr int kFinishMax = 1024;   // deepest approximations one work-group finishes on chip
+
+// Analysis, second stage: the first stage left the level-`lc` approximations
+// of a length-n signal either in FP32 at src32 or, when src32 is null, in
+// y[0, n_lc) (the prefix the deeper levels overwrite).  One work-group
+// computes levels lc+1..L in LDS (n_lc <= kFinishMax) with unnormalised
+// compensated sums as in the chunks, writing into the prefix of y.
+template <class S>
+__device__ void finish1d(typename S::raw* y, const float* src32, int64_t n, int lc, int L, df* buf0,
+                         df* buf1) {
+    const int t = threadIdx.x;
+    const int64_t m = ceil_shift(n, lc);
+    const int lr = L - lc;
+    for (int64_t i = t; i < m; i += blockDim.x) buf0[i] = df_from(src32 ? src32[i] : ld1<S>(y + i));
+    __syncthreads();
+    df* a = buf0;
+    df* b = buf1;
+    int64_t len = m;
+    for (int lev = 1; lev <= lr; ++lev) {
+        const int64_t half = len >> 1, na = len - half;   // na = offset of this level's details
+        for (int64_t P = t; P < na; P += blockDim.x) {
+            if (P < half) {
+                st1<S>(y + na + P, f_norm(df_diff(a[2 * P + 1], a[2 * P]), lev));
+                b[P] = df_add(a[2 * P], a[2 * P + 1]);
+            } else {
+                b[P] = df_s2(a[2 * P]);             // carried sample
+            }
+        }
+        __syncthreads();
+        df* tmp = a;
+        a = b;
+        b = tmp;
+        len = na;
+    }
+    for (int64_t P = t; P < len; P += blockDim.x) st1<S>(y + P, df_norm(a[P], lr));
+}
+
+// Synthesis: the level-lc approximation with index c of a length-n signal
+// transformed to L levels, from a_L down its ancestor path (one synthesis
+// butterfly per level; the odd-count carry passes values unchanged).  All
+// loads are issued before the arithmetic.  L - lc <= kMaxWalk.
+constexpr int kMaxWalk = 24;
+template <class S>
+__device__ __forceinline__ float walk_down(const typename S::raw* y, int64_t n, int L, int lc,
+                                           int64_t c) {
+    float dv[kMaxWalk];
+#pragma unroll
+    for (int q = 0; q < kMaxWalk; ++q) {
+        const int j = L - q;                      // detail level
+        dv[q] = 0.0f;
+        if (j > lc) {
+            const int64_t P = c >> (j - lc);
+            if (2 * P + 1 < ceil_shift(n, j - 1)) dv[q] = ld1<S>(y + ceil_shift(n, j) + P);
+        }
+    }
+    float a = ld1<S>(y + (c >> (L - lc)));
+#pragma unroll
+    for (int q = 0; q < kMaxWalk; ++q) {
+        const int j = L - q;
+        if (j > lc) {
+            const int64_t k = c >> (j - 1 - lc);  // index at level j-1
+            if (2 * (k >> 1) + 1 < ceil_shift(n, j - 1))
+                a = (k & 1) ? (a + dv[q]) * kRs2Hi : (a - dv[q]) * kRs2Hi;
+        }
+    }
+    return a;
 }
 
 }  // namespace haar

@@ -240,14 +240,68 @@ static int vec_ok_1d(const Pass1D& p, bool inverse, int ebx, int ebd, const Chun
     return ok ? 1 : 0;
 }
 
+// One chunk pass over every item (levels <= on-chip depth), shared by the
+// single-pass case and the first stage of the scratch-free deep analysis.
+static Pass1D chunk_pass(const void* in, void* out, int64_t N, int lv, int64_t batch, bool inverse,
+                         const Chunk1D& cc) {
+    Pass1D p{};
+    p.n = N;
+    p.batch = batch;
+    p.levels = lv;
+    p.det = const_cast<void*>(inverse ? in : (const void*)out);
+    p.det_bstride = N;
+    p.ll = const_cast<void*>(inverse ? in : (const void*)out);
+    p.ll_bstride = N;
+    if (!inverse) { p.src = in; p.src_bstride = N; }
+    else { p.dst = out; p.dst_bstride = N; }
+    p.remap = cc.remap;
+    p.chunks_per_item = (N + cc.chunk() - 1) / cc.chunk();
+    p.total_chunks = p.chunks_per_item * batch;
+    return p;
+}
+
 int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype, bool inverse,
            hipStream_t s, int cfg_override) {
     const int eb = elem_bytes(dtype);
     const int cfg = cfg_override >= 0 ? cfg_override : choose_config_1d(dtype, inverse, N, L);
     const Chunk1D cc = chunk_config_1d(cfg);
-    const std::vector<Region1D> ps = passes_1d(N, L, log2_int(cc.chunk()));
-    const int np = (int)ps.size();
+    const int depth = log2_int(cc.chunk());
 
+    // Deep transforms in two stages: the analysis chunks leave their
+    // level-`depth` approximations in the output prefix (FP32 storage) or in
+    // a small FP32 buffer (16-bit storage), and one work-group per item
+    // finishes them on chip; the synthesis walks each chunk's ancestor path
+    // from a_L.
+    if (L > depth && !inverse && ceil_shift_host(N, depth) <= kFinishMaxHost) {
+        Pass1D p = chunk_pass(in, out, N, depth, batch, false, cc);
+        const int64_t m = ceil_shift_host(N, depth);
+        void* a32 = nullptr;
+        if (dtype != HAAR_F32) {
+            hipError_t e = hipMallocAsync(&a32, (size_t)(batch * m * 4), s);
+            if (e != hipSuccess) return hip_error(e, "hipMallocAsync (level approximations)");
+            p.ll = a32;
+            p.ll_bstride = m;
+        }
+        p.vec_ok = vec_ok_1d(p, false, eb, a32 ? 4 : eb, cc);
+        hipError_t e = launch_fwd1d(p, dtype, cfg, false, a32 != nullptr, s);
+        if (e == hipSuccess) e = launch_finish1d(p, dtype, depth, L, a32 != nullptr, s);
+        int rc = e == hipSuccess ? HAAR_OK : hip_error(e, "fwd1d launch");
+        if (a32) {
+            e = hipFreeAsync(a32, s);
+            if (e != hipSuccess && rc == HAAR_OK) rc = hip_error(e, "hipFreeAsync");
+        }
+        return rc;
+    }
+    if (L > depth && inverse && L - depth <= kMaxWalkHost) {
+        Pass1D p = chunk_pass(in, out, N, depth, batch, true, cc);
+        p.levels_total = L;
+        p.vec_ok = vec_ok_1d(p, true, eb, eb, cc);
+        hipError_t e = launch_inv1d_walk(p, dtype, cfg, s);
+        return e == hipSuccess ? HAAR_OK : hip_error(e, "inv1d launch");
+    }
+
+    const std::vector<Region1D> ps = passes_1d(N, L, depth);
+    const int np = (int)ps.size();
     void* scratch = nullptr;
     int64_t half = 0;
     if (np > 1) {

@@ -35,6 +35,7 @@ struct Pass1D {
     int32_t vec_ok;
     int64_t chunks_per_item, total_chunks;
     int32_t remap;                          // deal contiguous chunk ranges to each XCD
+    int32_t levels_total;                   // synthesis with walk: all levels of the transform
 };
 
 // Tile shapes of the 2D kernels (per storage width): rows/cols per thread
@@ -70,5 +71,14 @@ int num_chunk_configs_1d();
 Chunk1D chunk_config_1d(int index);
 hipError_t launch_fwd1d(const Pass1D& p, int dtype, int cfg, bool x_f32, bool ll_f32, hipStream_t s);
 hipError_t launch_inv1d(const Pass1D& p, int dtype, int cfg, bool x_f32, bool ll_f32, hipStream_t s);
+// Deep 1D in two stages.  finish: levels lc+1..L of every item (one
+// work-group per item) into the prefix of p.det; the level-lc input is the
+// FP32 buffer p.ll when src32, else that prefix itself.
+// walk: one synthesis pass whose chunks derive their deepest approximation
+// from a_L (p.levels = chunk depth, p.levels_total = L).
+constexpr int kFinishMaxHost = 1024;
+constexpr int kMaxWalkHost = 24;
+hipError_t launch_finish1d(const Pass1D& p, int dtype, int lc, int L, bool src32, hipStream_t s);
+hipError_t launch_inv1d_walk(const Pass1D& p, int dtype, int cfg, hipStream_t s);
 
 }  // namespace haar

@@ -10,9 +10,9 @@
 // 1D items deeper than one chunk (levels > 12 with 4096-sample chunks):
 //   analysis  -- every chunk leaves its level-12 approximation in the item's
 //                output (the prefix that the deeper levels later overwrite);
-//                the last chunk of the item to finish (per-item counter,
-//                device-scope fences) computes the remaining levels of that
-//                prefix on chip;
+//                a second kernel, one work-group per deep item, computes the
+//                remaining levels of that prefix on chip (the kernel boundary
+//                orders the writes; no device-scope fences in the hot loop);
 //   synthesis -- every chunk derives its own level-12 approximation by
 //                walking down its ancestor path from a_L (one synthesis
 //                butterfly per level), then runs its 12 on-chip levels.
@@ -48,6 +48,7 @@ struct PlanItem1D {
     int32_t chunk_levels;  // levels done inside one chunk: min(levels, 12)
     int32_t nchunks;
     int32_t vec_ok;
+    int64_t a32;           // deep items: offset of their level-12 values in the FP32 area
 };
 struct PlanChunk1D {
     int32_t item, chunk;
@@ -55,11 +56,9 @@ struct PlanChunk1D {
 
 constexpr int kPlanNT1 = 256, kPlanE1 = 16;              // 1D chunk: 4096 samples
 constexpr int kPlanC1 = kPlanNT1 * kPlanE1, kPlanLogC1 = 12;
-constexpr int kFinishMax = 1024;                          // on-chip finish: n / 4096 <= 1024
 
 // ---------------------------------------------------------------------------
-// Counters: ctr[0] = next work unit, ctr[1] = work-groups done,
-// ctr[2 + i] = finished chunks of 1D item i.
+// Counters: ctr[0] = next work unit, ctr[1] = work-groups done.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool claim(unsigned* ctr, unsigned* s_slot, unsigned total, unsigned& unit) {
     if (threadIdx.x == 0) *s_slot = atomicAdd(&ctr[0], 1u);
@@ -142,50 +141,14 @@ __global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __rest
 // ---------------------------------------------------------------------------
 // 1D
 // ---------------------------------------------------------------------------
-// The remaining levels of a deep item on its prefix y[0, n12) (the chunks'
-// level-12 approximations), in place, by one work-group.
-template <class S>
-__device__ void finish1d(const PlanItem1D& it, df* buf0, df* buf1) {
-    using raw = typename S::raw;
-    raw* y = reinterpret_cast<raw*>(it.out);
-    const int t = threadIdx.x;
-    const int64_t n12 = ceil_shift(it.n, kPlanLogC1);
-    const int lr = it.levels - kPlanLogC1;
-    for (int64_t i = t; i < n12; i += blockDim.x) buf0[i] = df_from(ld1<S>(y + i));
-    __syncthreads();
-    df* a = buf0;
-    df* b = buf1;
-    int64_t len = n12;
-    for (int lev = 1; lev <= lr; ++lev) {
-        const int64_t half = len >> 1, na = len - half;
-        const int64_t ns = ceil_shift(n12, lev);     // == na: offset of this level's details
-        for (int64_t P = t; P < na; P += blockDim.x) {
-            if (P < half) {
-                st1<S>(y + ns + P, f_norm(df_diff(a[2 * P + 1], a[2 * P]), lev));
-                b[P] = df_add(a[2 * P], a[2 * P + 1]);
-            } else {
-                b[P] = df_s2(a[2 * P]);             // carried sample
-            }
-        }
-        __syncthreads();
-        df* tmp = a;
-        a = b;
-        b = tmp;
-        len = na;
-    }
-    for (int64_t P = t; P < len; P += blockDim.x) st1<S>(y + P, df_norm(a[P], lr));
-}
-
 template <class S, bool INV>
 __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __restrict__ items,
                                                          const PlanChunk1D* __restrict__ chunks,
-                                                         unsigned nunits, unsigned* ctr) {
+                                                         unsigned nunits, unsigned* ctr, float* a32) {
     constexpr int NW = kPlanNT1 / 64;
     __shared__ df smd[NW];
     __shared__ float smf[NW * 8];
-    __shared__ df fin0[INV ? 1 : kFinishMax];
-    __shared__ df fin1[INV ? 1 : kFinishMax];
-    __shared__ unsigned s_slot, s_last;
+    __shared__ unsigned s_slot;
     unsigned unit;
     while (claim(ctr, &s_slot, nunits, unit)) {
         const PlanChunk1D d = chunks[unit];
@@ -197,70 +160,55 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
         p.vec_ok = it.vec_ok;
         const bool full = it.vec_ok && (int64_t)(d.chunk + 1) * kPlanC1 <= it.n;
         if (!INV) {
+            // deep items: the chunk's level-12 approximation goes to the
+            // FP32 area; a second kernel finishes the deeper levels
             p.src = it.in;
             p.det = it.out;
-            p.ll = it.out;
-            if (full)
-                fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd);
-            else
-                fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd);
             if (it.levels > it.chunk_levels) {
-                __threadfence();            // this chunk's level-12 value, device-wide
-                __syncthreads();
-                if (threadIdx.x == 0)
-                    s_last = atomicAdd(&ctr[2 + d.item], 1u) == (unsigned)(it.nchunks - 1);
-                __syncthreads();
-                if (s_last) {
-                    __threadfence();        // see the other chunks' values
-                    finish1d<S>(it, fin0, fin1);
-                    if (threadIdx.x == 0) atomicExch(&ctr[2 + d.item], 0u);
-                }
+                p.ll = a32 + it.a32;
+                if (full)
+                    fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd);
+                else
+                    fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd);
+            } else {
+                p.ll = it.out;
+                if (full)
+                    fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd);
+                else
+                    fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd);
             }
         } else {
             p.det = const_cast<void*>(it.in);
             p.ll = const_cast<void*>(it.in);
             p.dst = it.out;
-            bool has_top = false;
-            float top = 0.0f;
-            if (it.levels > it.chunk_levels) {
-                // a_12[chunk] from a_L down the ancestor path (all loads first)
-                using raw = typename S::raw;
-                const raw* y = reinterpret_cast<const raw*>(it.in);
-                const int L = it.levels;
-                const int64_t c = d.chunk;
-                float dv[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int j = L - q;                    // detail level
-                    dv[q] = 0.0f;
-                    if (j > kPlanLogC1) {
-                        const int64_t P = c >> (j - kPlanLogC1);
-                        const int64_t len = ceil_shift(it.n, j - 1);
-                        if (2 * P + 1 < len) dv[q] = ld1<S>(y + ceil_shift(it.n, j) + P);
-                    }
-                }
-                float a = ld1<S>(y + (c >> (L - kPlanLogC1)));
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int j = L - q;
-                    if (j > kPlanLogC1) {
-                        const int64_t k = c >> (j - 1 - kPlanLogC1);   // index at level j-1
-                        const int64_t P = k >> 1;
-                        const int64_t len = ceil_shift(it.n, j - 1);
-                        if (2 * P + 1 < len) a = (k & 1) ? (a + dv[q]) * kRs2Hi : (a - dv[q]) * kRs2Hi;
-                    }
-                }
-                has_top = true;
-                top = a;
-            }
+            const bool deep = it.levels > it.chunk_levels;
+            const float top = deep ? walk_down<S>(reinterpret_cast<const typename S::raw*>(it.in), it.n,
+                                                  it.levels, kPlanLogC1, d.chunk)
+                                   : 0.0f;
             if (full)
-                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smf, has_top, top);
+                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smf, deep, top);
             else
-                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smf, has_top, top);
+                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smf, deep, top);
         }
         __syncthreads();
     }
     retire(ctr);
+}
+
+// Second kernel of a 1D analysis plan: the levels beyond 12 of each deep
+// item, one work-group per item (the kernel boundary orders the chunks'
+// writes before these reads).
+template <class S>
+__global__ __launch_bounds__(256) void plan1d_finish_kernel(const PlanItem1D* __restrict__ items,
+                                                            const int32_t* __restrict__ deep,
+                                                            unsigned ndeep, const float* a32) {
+    __shared__ df buf0[kFinishMax], buf1[kFinishMax];
+    for (unsigned i = blockIdx.x; i < ndeep; i += gridDim.x) {
+        const PlanItem1D it = items[deep[i]];
+        finish1d<S>(reinterpret_cast<typename S::raw*>(it.out), a32 + it.a32, it.n, kPlanLogC1, it.levels,
+                    buf0, buf1);
+        __syncthreads();
+    }
 }
 
 }  // namespace haar
@@ -279,7 +227,8 @@ struct haar_plan {
     std::vector<PlanTile2D> tiles2[2];  // per tile configuration
     std::vector<PlanItem1D> items1;
     std::vector<PlanChunk1D> chunks1;
-    size_t off_items = 0, off_units = 0, ws_bytes = 0;
+    std::vector<int32_t> deep1;        // 1D items with more than 12 levels
+    size_t off_items = 0, off_units = 0, off_deep = 0, off_a32 = 0, ws_bytes = 0;
     int64_t nunits = 0;
     int grid = 0;
     bool uploaded = false;
@@ -330,15 +279,22 @@ hipError_t launch_plan1d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
     const PlanItem1D* items = (const PlanItem1D*)((char*)ws + pl->off_items);
     const PlanChunk1D* chunks = (const PlanChunk1D*)((char*)ws + pl->off_units);
     unsigned* ctr = (unsigned*)ws;
+    float* a32 = (float*)((char*)ws + pl->off_a32);
     const unsigned n = (unsigned)pl->nunits;
     auto go = [&](auto kernel) -> hipError_t {
         const int g = std::min<int64_t>(grid_for(kernel, kPlanNT1), std::max<int64_t>(1, n));
         if (grid) *grid = g;
         if (query_only) return hipSuccess;
-        hipLaunchKernelGGL(kernel, dim3(g), dim3(kPlanNT1), 0, s, items, chunks, n, ctr);
+        hipLaunchKernelGGL(kernel, dim3(g), dim3(kPlanNT1), 0, s, items, chunks, n, ctr, a32);
         return hipGetLastError();
     };
-    return pl->inverse ? go(plan1d_kernel<S, true>) : go(plan1d_kernel<S, false>);
+    if (pl->inverse) return go(plan1d_kernel<S, true>);
+    hipError_t e = go(plan1d_kernel<S, false>);
+    if (e != hipSuccess || query_only || pl->deep1.empty()) return e;
+    const int32_t* deep = (const int32_t*)((char*)ws + pl->off_deep);
+    const unsigned nd = (unsigned)pl->deep1.size();
+    hipLaunchKernelGGL(plan1d_finish_kernel<S>, dim3(nd), dim3(256), 0, s, items, deep, nd, a32);
+    return hipGetLastError();
 }
 
 hipError_t launch_plan(const haar_plan* pl, void* ws, hipStream_t s, bool query_only, int* grid) {
@@ -477,6 +433,7 @@ int haar_plan_create_1d(const haar_item_1d* items, int64_t count, int32_t dtype,
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int64_t a, int64_t b) { return items[a].length > items[b].length; });
+    int64_t a32_floats = 0;
     for (int64_t oi = 0; oi < count; ++oi) {
         const haar_item_1d& it = items[order[oi]];
         PlanItem1D pi{};
@@ -494,11 +451,19 @@ int haar_plan_create_1d(const haar_item_1d* items, int64_t count, int32_t dtype,
             ok = ok && ceil_shift_host(it.length, lev) % v == 0;
         }
         pi.vec_ok = ok ? 1 : 0;
+        pi.a32 = -1;
+        if (pi.levels > pi.chunk_levels) {
+            pl->deep1.push_back((int32_t)oi);
+            pi.a32 = a32_floats;
+            a32_floats += (pi.nchunks + 63) & ~63;
+        }
         pl->items1.push_back(pi);
         for (int32_t c = 0; c < pi.nchunks; ++c) pl->chunks1.push_back(PlanChunk1D{(int32_t)oi, c});
     }
-    layout(pl, sizeof(PlanItem1D), pl->items1.size(), sizeof(PlanChunk1D), (int64_t)pl->chunks1.size(),
-           2 + (size_t)count);
+    layout(pl, sizeof(PlanItem1D), pl->items1.size(), sizeof(PlanChunk1D), (int64_t)pl->chunks1.size(), 2);
+    pl->off_deep = pl->ws_bytes;
+    pl->off_a32 = align256(pl->off_deep + sizeof(int32_t) * (pl->deep1.size() + 1));
+    pl->ws_bytes = align256(pl->off_a32 + sizeof(float) * (size_t)a32_floats);
     *out = pl;
     return HAAR_OK;
 }
@@ -529,6 +494,9 @@ int haar_plan_upload(haar_plan* plan, void* workspace, void* stream) {
     } else {
         e = hipMemcpyAsync(ws + plan->off_units, plan->chunks1.data(),
                            plan->chunks1.size() * sizeof(PlanChunk1D), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && !plan->deep1.empty())
+            e = hipMemcpyAsync(ws + plan->off_deep, plan->deep1.data(),
+                               plan->deep1.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
     }
     if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync (plan work-list)");
     plan->uploaded = true;

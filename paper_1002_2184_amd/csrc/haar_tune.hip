@@ -64,7 +64,6 @@ int choose_config_1d(int dtype, bool inverse, int64_t n, int levels) {
     // default: the smallest chunk that holds the signal, 4096 samples beyond
     if (n <= 1024) return 2;
     if (n <= 2048) return 3;
-    if (n > 4096 && n <= 16384 && levels > 12) return 1;
     return 0;
 }
 
