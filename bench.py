@@ -4,9 +4,11 @@ One step = the whole hot path on one synthetic input: the 5-level separable
 2D analysis of a 4096 x 4096 FP32 smooth image followed by its synthesis
 (fwd + inv).  Throughput is effective bandwidth: the algorithmic bytes of a
 step (each direction reads its input once and writes its output once,
-4 * N * 4 bytes) divided by the step time.  Inputs are resident in HBM; four
-buffer sets rotate so that the data of a step was last touched three steps
-earlier (768 MiB in between, three times the 256 MB Infinity Cache).
+4 * N * 4 bytes) divided by the step time.  Inputs are resident in HBM; 16
+buffer sets rotate so that the data of a step was last touched 15 steps
+earlier.  Many sets are needed because the kernels store with nontemporal
+hints: their outputs never enter the 256 MB Infinity Cache, so only reads
+evict it, and with few sets a step's input is still cached from its last use.
 
 Printed: one JSON line with the contract fields, a ``roofline`` object for
 the dominant kernel (timed per launch with HIP events on the launch stream),
@@ -31,7 +33,7 @@ METRIC = "effective GB/s & % HBM peak, Haar fwd+inv 2D 4096² 5-level; fwd+bwd v
 H = W = 4096
 LEVELS = 5
 PEAK_GBPS = 8000.0          # MI355X HBM3E, 8 TB/s
-SETS = 4
+SETS = 16
 KERNEL_SOURCES = ["paper_1002_2184_amd/csrc/haar_2d.hip", "paper_1002_2184_amd/csrc/haar_2d_tile.h",
                   "paper_1002_2184_amd/csrc/haar_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd2d_inv2d_4096x4096_L5.json")
@@ -137,6 +139,24 @@ def write_traffic(fetch_csv: str, write_csv: str, command: str):
         f.write(f"\nKernel sources sha256[:16] = {kernel_hash()} (bench.py reports traffic only "
                 f"while the sources match).\n")
     print(json.dumps(doc))
+
+
+def write_kernel_stats(stats_csv: str, command: str, out_md: str):
+    """Summarise a rocprofv3 --kernel-trace --stats CSV (one row per kernel
+    name) into a short Markdown table under profiles/."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    with open(out_md, "w") as f:
+        f.write(f"# Kernel durations (rocprofv3 --kernel-trace --stats)\n\nCommand: `{command}`\n\n")
+        f.write("| kernel | calls | average us | min us | max us | share of GPU time |\n|---|---|---|---|---|---|\n")
+        for r in rows:
+            name = r["Name"]
+            short = name if len(name) <= 110 else name[:107] + "..."
+            f.write(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                    f"{float(r['Percentage']):.1f} % |\n")
+    print(open(out_md).read())
 
 
 def _timed(fn, reps, warm, stream):
@@ -300,11 +320,16 @@ def main():
                     help="run the dispatches profiled by the rocprofv3 counter passes and exit")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="summarise two rocprofv3 counter CSVs into the profiles/ traffic file")
+    ap.add_argument("--write-kernel-stats", nargs=3, metavar=("STATS_CSV", "COMMAND", "OUT_MD"),
+                    help="summarise a rocprofv3 kernel stats CSV into a Markdown table")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads (1D latency, batched, autograd, BF16) and exit")
     args = ap.parse_args()
     if args.suite:
         suite()
+        return
+    if args.write_kernel_stats:
+        write_kernel_stats(*args.write_kernel_stats)
         return
     if args.write_traffic:
         write_traffic(*args.write_traffic)
@@ -337,16 +362,10 @@ def main():
     alg_step = 4.0 * n * 4          # fwd: read + write; inv: read + write (FP32)
     alg_launch = 2.0 * n * 4
 
-    def step(k, ev=None):
+    def step(k):
         s = k % SETS
-        if ev is not None:
-            ev[0].record(stream)
         T.fwd2d(xs[s], LEVELS, out=ys[s])
-        if ev is not None:
-            ev[1].record(stream)
         T.inv2d(ys[s], LEVELS, out=zs[s])
-        if ev is not None:
-            ev[2].record(stream)
 
     for k in range(args.warmup):
         step(k)
@@ -364,20 +383,30 @@ def main():
     ms_step = t_start.elapsed_time(t_end) / args.steps
     gbps = alg_step / (ms_step * 1e-3) / 1e9
 
-    # per-launch HIP events on the launch stream (same steps again)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    for k in range(args.steps):
-        step(k, evs[k])
-    torch.cuda.synchronize()
-    fwd_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    inv_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    # average duration of each kernel: K back-to-back launches of it alone,
+    # bracketed by HIP events on the launch stream (the sets still rotate,
+    # so every launch reads data last touched 15 launches earlier)
+    def per_launch_ms(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for k in range(args.steps):
+            fn(k % SETS)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    fwd_avg = per_launch_ms(lambda s: T.fwd2d(xs[s], LEVELS, out=ys[s]))
+    inv_avg = per_launch_ms(lambda s: T.inv2d(ys[s], LEVELS, out=zs[s]))
 
     # correctness spot check of the timed outputs (GPU side)
     rt_err = float((zs[0] - xs[0]).abs().max() / xs[0].pow(2).mean().sqrt())
 
     # autograd fwd + bwd (backward = synthesis on the upstream gradient); the
-    # upstream gradients rotate with the inputs so every step reads cold data
+    # upstream gradients rotate with the inputs so every step reads cold data.
+    # Eager steps are bound by the host (autograd bookkeeping, allocation);
+    # the graph-captured step measures the device work of the same calls.
     gs = [torch.randn(H, W, device=dev) for _ in range(SETS)]
     xr = [x.clone().requires_grad_(True) for x in xs]
 
@@ -387,20 +416,47 @@ def main():
         (gx,) = torch.autograd.grad(y, xr[s], gs[s])
         return gx
 
+    def timed_loop(fn):
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a0.record(stream)
+        for k in range(args.steps):
+            fn(k)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / args.steps
+
     for k in range(args.warmup):
         ag_step(k)
     torch.cuda.synchronize()
+    ag_eager_ms = timed_loop(ag_step)
+
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        for k in range(3):
+            ag_step(k)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()          # one replay = one step on each buffer set
+    with torch.cuda.graph(graph):
+        for s_ in range(SETS):
+            ag_step(s_)
+    torch.cuda.synchronize()
+    graph.replay()
+    reps = max(1, args.steps // SETS)
     a0 = torch.cuda.Event(enable_timing=True)
     a1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     a0.record(stream)
-    for k in range(args.steps):
-        ag_step(k)
+    for _ in range(reps):
+        graph.replay()
     a1.record(stream)
     torch.cuda.synchronize()
-    ag_ms = a0.elapsed_time(a1) / args.steps
+    ag_ms = a0.elapsed_time(a1) / (reps * SETS)
     ag_gbps = alg_step / (ag_ms * 1e-3) / 1e9
 
-    fwd_avg, inv_avg = float(np.mean(fwd_ms)), float(np.mean(inv_ms))
     dom, dom_ms = ("fwd2d", fwd_avg) if fwd_avg >= inv_avg else ("inv2d", inv_avg)
     achieved = alg_launch / (dom_ms * 1e-3) / 1e9
     traffic = load_traffic(dom)
@@ -419,7 +475,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2d-smooth-4096x4096-L5 fwd+inv", "height": H, "width": W,
                    "levels": LEVELS, "storage": "f32", "buffer_sets": SETS,
-                   "cold_cache": "4 rotating buffer sets, 768 MiB between reuses"},
+                   "cold_cache": f"{SETS} rotating buffer sets, {(SETS - 1) * 2 * n * 4 >> 20} MiB "
+                                 "read between reuses of a set"},
         "pct_of_hbm_peak": round(100.0 * gbps / PEAK_GBPS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
@@ -428,7 +485,10 @@ def main():
                      "bytes_per_launch": int(alg_launch)},
         "kernels_avg_us": {"fwd2d": round(fwd_avg * 1e3, 3), "inv2d": round(inv_avg * 1e3, 3)},
         "fwd_bwd": {"value": round(ag_gbps, 2), "unit": "GB/s", "ms_per_step": round(ag_ms, 5),
-                    "vs_plain_fwd_inv": round(ag_gbps / gbps, 4)},
+                    "vs_plain_fwd_inv": round(ag_gbps / gbps, 4),
+                    "how": "HaarFwd2D.apply + torch.autograd.grad on each buffer set, captured in one HIP graph",
+                    "eager_ms_per_step": round(ag_eager_ms, 5),
+                    "eager_value": round(alg_step / (ag_eager_ms * 1e-3) / 1e9, 2)},
         "roundtrip_max_err_over_rms": rt_err,
     }
     if not args.no_cpu:
