@@ -48,10 +48,18 @@
  *   enqueues nothing and returns HAAR_OK.
  * Threading.  All entry points are reentrant; the tuning table is guarded by
  *   a mutex.
- * Scratch.  Transforms deeper than one fused pass (2D levels > 5; 1D levels
- *   beyond the on-chip depth of one work-group) keep intermediate
- *   approximations in stream-ordered scratch obtained with hipMallocAsync on
- *   `stream` and released with hipFreeAsync on the same stream.
+ * Scratch.  Most calls allocate nothing.  Three cases keep intermediate
+ *   values in stream-ordered scratch obtained with hipMallocAsync on `stream`
+ *   and released with hipFreeAsync on the same stream: 2D transforms deeper
+ *   than one fused pass (levels > 5); 1D analyses deeper than one chunk
+ *   (levels > 12 at the default 4096-sample chunk) in BF16/FP16 storage (one
+ *   FP32 value per chunk) or on more than 1024 chunks per signal; and 1D
+ *   syntheses more than 24 levels deeper than one chunk.
+ * Deep 1D.  A 1D analysis deeper than one chunk runs as two kernels: the
+ *   chunks, then one work-group per signal computing the remaining levels of
+ *   the chunk approximations on chip.  The matching synthesis is one kernel:
+ *   every chunk derives its own deepest approximation from a_L along its
+ *   ancestor path.
  */
 #ifndef HAAR_H_
 #define HAAR_H_
@@ -123,7 +131,9 @@ int haar_max_levels_2d(int64_t height, int64_t width);
  * A plan lists the work units of all items (2D: tiles, 1D: chunks of 4096
  * samples), largest items first, and haar_plan_execute() enqueues ONE
  * persistent kernel whose work-groups claim units with an atomic counter
- * until the list is exhausted.  The plan itself holds host memory only; the
+ * until the list is exhausted (a 1D analysis plan with items deeper than 12
+ * levels enqueues a second, small kernel that finishes those items, one
+ * work-group per item).  The plan itself holds host memory only; the
  * device-side tables and counters live in a caller-owned workspace of
  * haar_plan_workspace_size() bytes (256-byte aligned).
  *
@@ -139,8 +149,8 @@ int haar_max_levels_2d(int64_t height, int64_t width);
  * Limits: 2D items 1 <= levels <= min(5, haar_max_levels_2d); 1D items
  * 1 <= levels <= min(20, haar_max_levels_1d), and items with more than 12
  * levels at most 1024 * 4096 samples long (HAAR_ERR_UNSUPPORTED otherwise).
- * 1D items with more than 12 levels keep their level-12 approximation in the
- * storage type between the on-chip stages.
+ * 1D items with more than 12 levels keep their level-12 approximation in
+ * FP32 in the workspace between the two kernels.
  * ------------------------------------------------------------------------ */
 typedef struct {
     const void* in;   /* [length] input (device)                */
