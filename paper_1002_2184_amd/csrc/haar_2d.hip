@@ -47,7 +47,7 @@ __device__ __forceinline__ void tile_coords(const Pass2D& p, int64_t tile, int64
 // before it computes and writes the current one, so that reads stay in
 // flight while the tile's LDS levels and stores run.  Edge launches process
 // one tile per work-group on the scalar path.
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE, bool PIPE>
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE, bool PIPE, int MAP>
 __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D p, int64_t ntiles) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
     __shared__ float sm[G::SMEM];
@@ -57,21 +57,21 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D
     int64_t item, ty, tx;
     tile_coords<EDGE>(p, remap ? xcd_tile(b, ntiles) : b, item, ty, tx);
     FwdIn<RY, RX> cur;
-    fwd2d_load<SX, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, cur);
+    fwd2d_load<SX, RY, RX, GY, GX, !EDGE, MAP>(p, item, ty, tx, cur);
     while (true) {
         const int64_t nb = b + gridDim.x;
         int64_t nitem = 0, nty = 0, ntx = 0;
         FwdIn<RY, RX> nxt;
         if (PIPE && nb < ntiles) {
             tile_coords<EDGE>(p, nb, nitem, nty, ntx);
-            fwd2d_load<SX, RY, RX, GY, GX, !EDGE>(p, nitem, nty, ntx, nxt);
+            fwd2d_load<SX, RY, RX, GY, GX, !EDGE, MAP>(p, nitem, nty, ntx, nxt);
         }
-        fwd2d_body<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, cur, sm);
+        fwd2d_body<SX, SD, SL, RY, RX, GY, GX, !EDGE, MAP>(p, item, ty, tx, cur, sm);
         if (nb >= ntiles) break;
         __syncthreads();
         if (!PIPE) {
             tile_coords<EDGE>(p, nb, nitem, nty, ntx);
-            fwd2d_load<SX, RY, RX, GY, GX, !EDGE>(p, nitem, nty, ntx, nxt);
+            fwd2d_load<SX, RY, RX, GY, GX, !EDGE, MAP>(p, nitem, nty, ntx, nxt);
         }   // LDS reuse by the next tile
         cur = nxt;
         b = nb;
@@ -119,35 +119,42 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D
 // ---------------------------------------------------------------------------
 // Tile-shape table and launchers
 // ---------------------------------------------------------------------------
-// Index -> (GY, GX, XCD remap, work-groups per CU); RY = 4 and RX = 16 bytes
-// / element size.  Work-groups per CU = 0: one tile per work-group; k > 0: a
-// persistent interior grid of k work-groups per compute unit.
-#define HAAR_2D_TILES(X)   \
-    X(0, 8, 32, 0, 0)      \
-    X(1, 8, 64, 0, 0)      \
-    X(2, 8, 32, 0, 4)      \
-    X(3, 8, 64, 0, 2)      \
-    X(4, 8, 32, 0, 2)      \
-    X(5, 8, 32, 1, 0)      \
-    X(6, 8, 16, 0, 8)      \
-    X(7, 16, 16, 1, 0)
+// Index -> (GY, GX, XCD remap, work-groups per CU, analysis thread map);
+// RY = 4 and RX = 16 bytes / element size.  Work-groups per CU = 0: one tile
+// per work-group; k > 0: a persistent interior grid of k work-groups per
+// compute unit.  Map 1: wavefront-local analysis (see thread_rc).
+#define HAAR_2D_TILES(X)      \
+    X(0, 8, 32, 0, 0, 0)      \
+    X(1, 8, 64, 0, 0, 0)      \
+    X(2, 8, 32, 0, 4, 0)      \
+    X(3, 8, 64, 0, 2, 0)      \
+    X(4, 8, 32, 0, 2, 0)      \
+    X(5, 8, 32, 1, 0, 0)      \
+    X(6, 8, 16, 0, 8, 0)      \
+    X(7, 16, 16, 1, 0, 0)     \
+    X(8, 8, 64, 0, 0, 1)      \
+    X(9, 8, 32, 0, 0, 1)      \
+    X(10, 8, 16, 0, 0, 1)     \
+    X(11, 8, 8, 0, 0, 1)      \
+    X(12, 8, 16, 1, 0, 1)     \
+    X(13, 8, 8, 1, 0, 1)
 
-int num_tile_configs_2d(int) { return 8; }
+int num_tile_configs_2d(int) { return 14; }
 
 Tile2D tile_config_2d(int elem_bytes, int index) {
     const int rx = 16 / elem_bytes;
     switch (index) {
-#define X(I, GY_, GX_, RM_, WPC_) \
-    case I:                       \
-        return Tile2D{4, rx, GY_, GX_, RM_, WPC_};
+#define X(I, GY_, GX_, RM_, WPC_, MAP_) \
+    case I:                             \
+        return Tile2D{4, rx, GY_, GX_, RM_, WPC_, MAP_};
         HAAR_2D_TILES(X)
 #undef X
         default:
-            return Tile2D{4, rx, 8, 32, 0, 0};
+            return Tile2D{4, rx, 8, 32, 0, 0, 0};
     }
 }
 
-template <class SX, class SD, class SL, int GY, int GX, bool PIPE>
+template <class SX, class SD, class SL, int GY, int GX, bool PIPE, int MAP = 0>
 static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     constexpr int RX = 16 / SX::kBytes;
     constexpr int64_t kMaxGrid = 1 << 20;
@@ -160,7 +167,7 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
             hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE>), dim3(grid),
                                dim3(GY * GX), 0, s, p, interior);
         else
-            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE>), dim3(grid),
+            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE, MAP>), dim3(grid),
                                dim3(GY * GX), 0, s, p, interior);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -171,7 +178,7 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
             hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, true, false>), dim3(grid),
                                dim3(GY * GX), 0, s, p, edge);
         else
-            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, true, false>), dim3(grid),
+            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, true, false, MAP>), dim3(grid),
                                dim3(GY * GX), 0, s, p, edge);
         return hipGetLastError();
     }
@@ -181,9 +188,9 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
 template <class S>
 static hipError_t dispatch2d(const Pass2D& p, int cfg, bool inverse, hipStream_t s) {
     switch (cfg) {
-#define X(I, GY_, GX_, RM_, WPC_) \
-    case I:                       \
-        return launch2d<S, S, S, GY_, GX_, (WPC_ > 0)>(p, inverse, s);
+#define X(I, GY_, GX_, RM_, WPC_, MAP_) \
+    case I:                             \
+        return launch2d<S, S, S, GY_, GX_, (WPC_ > 0), MAP_>(p, inverse, s);
         HAAR_2D_TILES(X)
 #undef X
         default:

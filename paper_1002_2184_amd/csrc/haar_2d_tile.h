@@ -116,19 +116,43 @@ struct FwdIn {
     float v[RY][RX];
 };
 
-template <class SX, int RY, int RX, int GY, int GX, bool FULL>
+// Thread -> register block (row group rg, column group cg) of an analysis
+// tile.  MAP 0: row-major over the GY x GX groups (a wavefront spans 64
+// column groups, or two rows of 32).  MAP 1 (GY = 8): every wavefront owns an
+// 8 x 8 patch of groups, i.e. whole 32-row dependency blocks, so that all
+// levels of a full tile stay inside the wavefront.
+template <int GY, int GX, int MAP>
+__device__ __forceinline__ void thread_rc(int t, int& rg, int& cg) {
+    if constexpr (MAP == 0) {
+        rg = t / GX;
+        cg = t % GX;
+    } else {
+        static_assert(GY == 8 && GX % 8 == 0, "wavefront-local tiles are 8 x 8k groups");
+        const int lane = t & 63;
+        rg = lane >> 3;
+        cg = (t >> 6) * 8 + (lane & 7);
+    }
+}
+
+__device__ __forceinline__ df shfl_xor_df(df a, int m) {
+    return df{__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)};
+}
+
+template <class SX, int RY, int RX, int GY, int GX, bool FULL, int MAP = 0>
 __device__ __forceinline__ void fwd2d_load(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
                                            FwdIn<RY, RX>& in) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
     constexpr int TH = G::TH, TW = G::TW;
-    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
+    const int t = threadIdx.x;
+    int rg, cg;
+    thread_rc<GY, GX, MAP>(t, rg, cg);
     const int64_t r0 = ty * TH, c0 = tx * TW;
     const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
     const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
     const int lr0 = rg * RY, lc0 = cg * RX;
     const typename SX::raw* src =
         reinterpret_cast<const typename SX::raw*>(p.src) + item * p.src_bstride + r0 * p.src_pitch + c0;
-    if constexpr (FULL) {
+    if (FULL || (lr0 + RY <= th && lc0 + RX <= tw)) {   // whole register block inside
 #pragma unroll
         for (int r = 0; r < RY; ++r) ld_vec<SX, RX>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0, in.v[r]);
     } else {
@@ -142,19 +166,24 @@ __device__ __forceinline__ void fwd2d_load(const Pass2D& p, int64_t item, int64_
     }
 }
 
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL, int MAP = 0>
 __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
                                            const FwdIn<RY, RX>& in, float* sm) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
     constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
     constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
 
-    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
+    const int t = threadIdx.x;
+    int rg, cg;
+    thread_rc<GY, GX, MAP>(t, rg, cg);
     const int64_t r0 = ty * TH, c0 = tx * TW;
     const int L = p.levels;
     const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
     const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
     const int lr0 = rg * RY, lc0 = cg * RX;            // local origin of this thread's block
+    // the whole register block lies inside the region: every 2x2 block of
+    // levels 1 and 2 is complete and its bands are written as vectors
+    const bool inb = FULL || (lr0 + RY <= th && lc0 + RX <= tw);
 
     typename SD::raw* det = reinterpret_cast<typename SD::raw*>(p.det) + item * p.det_bstride;
     typename SL::raw* llp = reinterpret_cast<typename SL::raw*>(p.ll) + item * p.ll_bstride;
@@ -181,7 +210,7 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
             }
         const int64_t hs = ceil_shift(p.h, 1), ws = ceil_shift(p.w, 1);
         const int64_t R = (r0 >> 1) + (lr0 >> 1), C = (c0 >> 1) + (lc0 >> 1);
-        if constexpr (FULL) {
+        if (inb) {
 #pragma unroll
             for (int i = 0; i < B1Y; ++i) {
                 st_vec<SD, B1X>(det + (R + i) * dp + ws + C, hl[i]);
@@ -205,7 +234,7 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
         if (L == 1) {
 #pragma unroll
             for (int i = 0; i < B1Y; ++i) {
-                if constexpr (FULL) {
+                if (inb) {
                     float o[B1X];
 #pragma unroll
                     for (int k = 0; k < B1X; ++k) o[k] = df_round(a1[i][k]);
@@ -243,7 +272,7 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
             }
         const int64_t hs = ceil_shift(p.h, 2), ws = ceil_shift(p.w, 2);
         const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
-        if constexpr (FULL) {
+        if (inb) {
 #pragma unroll
             for (int i = 0; i < B2Y; ++i) {
                 st_vec<SD, B2X>(det + (R + i) * dp + ws + C, hl[i]);
@@ -267,7 +296,7 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
         if (L == 2) {
 #pragma unroll
             for (int i = 0; i < B2Y; ++i) {
-                if constexpr (FULL) {
+                if (inb) {
                     float o[B2X];
 #pragma unroll
                     for (int k = 0; k < B2X; ++k) o[k] = df_round(a2[i][k]);
@@ -283,6 +312,58 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
         }
     }
 
+    if constexpr (FULL && MAP == 1) {
+        // Levels 3..L inside the wavefront (a 32 x 8*RX patch of the tile):
+        // the 2x2 partners of a level sit at fixed lane distances, so every
+        // level is one round of xor-shuffles; no LDS, no barrier.  Shuffles run
+        // on all lanes (uniform control flow); the lanes holding a valid
+        // coefficient of the level store it.
+        const int lane = t & 63, w = t >> 6;
+        const int rgl = lane >> 3, cgl = lane & 7;
+        constexpr int CS3 = B2X == 1 ? 2 : 1;          // lane distance of adjacent level-3 columns
+        df x00, x01, x10, x11;
+        if constexpr (B2X == 1) {
+            x00 = a2[0][0];
+            x01 = shfl_xor_df(a2[0][0], 1);
+            x10 = shfl_xor_df(a2[0][0], 8);
+            x11 = shfl_xor_df(a2[0][0], 9);
+        } else {
+            x00 = a2[0][0];
+            x01 = a2[0][1];
+            x10 = shfl_xor_df(a2[0][0], 8);
+            x11 = shfl_xor_df(a2[0][1], 8);
+        }
+        int i = rgl >> 1, k = B2X == 1 ? (cgl >> 1) : cgl;   // level-3 position in the patch
+        bool active = (rgl & 1) == 0 && (B2X == 2 || (cgl & 1) == 0);
+        const int64_t wc0 = c0 + (int64_t)w * 8 * RX;         // first column of the patch
+        df ll;
+        float hl, lh, hh;
+#pragma unroll
+        for (int lev = 3; lev <= kMaxPassLevels2D; ++lev) {
+            if (lev > 3) {
+                const int cs = CS3 << (lev - 4), rs = 16 << (lev - 4);
+                x00 = ll;
+                x01 = shfl_xor_df(ll, cs);
+                x10 = shfl_xor_df(ll, rs);
+                x11 = shfl_xor_df(ll, cs | rs);
+                active = active && (i & 1) == 0 && (k & 1) == 0;
+                i >>= 1;
+                k >>= 1;
+            }
+            ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
+            if (active) {
+                const int64_t hs = ceil_shift(p.h, lev), ws = ceil_shift(p.w, lev);
+                const int64_t R = (r0 >> lev) + i, C = (wc0 >> lev) + k;
+                st1<SD>(det + R * dp + ws + C, hl);
+                st1<SD>(det + (hs + R) * dp + C, lh);
+                st1<SD>(det + (hs + R) * dp + ws + C, hh);
+                if (lev == L) st1<SL>(llp + R * lp + C, df_round(ll));
+            }
+            if (lev == L) return;
+        }
+        return;
+    }
+
     // ---- levels 3..L.  Buffer A holds LL2 (pitch TW/4), buffer B LL3 (pitch TW/8).
     float* Ahi = sm;
     float* Alo = sm + G::AN;
@@ -290,7 +371,7 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
     float* Blo = Bhi + G::BN;
     int rh = (th + 3) >> 2, rw = (tw + 3) >> 2;   // local region size at level 2
     int first = 3;                                // first level of the single-wave phase
-    if constexpr (FULL && GX == 32) {
+    if constexpr (FULL && GX == 32 && MAP == 0) {
         // Level 3 inside each wavefront: with 32 column groups a wave holds
         // LL2 rows 2w (lanes 0-31) and 2w+1 (lanes 32-63), so every 2x2 block
         // of LL2 lies in one wave: xor-shuffles fetch the partners.
@@ -368,11 +449,11 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
             float hl, lh, hh;
             ana_edge_df(x00, x01, x10, x11, r1, c1, ll, hl, lh, hh);
             const int64_t R = R0 + i, C = C0 + k;
-            if (c1) st1<SD>(det + R * dp + ws + C, hl);
-            if (r1) st1<SD>(det + (hs + R) * dp + C, lh);
-            if (r1 && c1) st1<SD>(det + (hs + R) * dp + ws + C, hh);
+            if (c1) st1_cached<SD>(det + R * dp + ws + C, hl);
+            if (r1) st1_cached<SD>(det + (hs + R) * dp + C, lh);
+            if (r1 && c1) st1_cached<SD>(det + (hs + R) * dp + ws + C, hh);
             if (lev == L) {
-                st1<SL>(llp + R * lp + C, df_round(ll));
+                st1_cached<SL>(llp + R * lp + C, df_round(ll));
             } else {
                 ohi[i * pout + k] = ll.hi;
                 olo[i * pout + k] = ll.lo;
@@ -428,6 +509,7 @@ __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_
     const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
     const int lr0 = rg * RY, lc0 = cg * RX;
     const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
+    const bool inb = FULL || (lr0 + RY <= th && lc0 + RX <= tw);   // whole block inside
     const typename SD::raw* det = reinterpret_cast<const typename SD::raw*>(p.det) + item * p.det_bstride;
     const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
     const int64_t dp = p.det_pitch, lp = p.ll_pitch;
@@ -491,7 +573,7 @@ __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_
         const int64_t R = (r0 >> 1) + (lr0 >> 1), C = (c0 >> 1) + (lc0 >> 1);
 #pragma unroll
         for (int i = 0; i < B1Y; ++i) {
-            if constexpr (FULL) {
+            if (inb) {
                 ld_vec<SD, B1X>(det + (R + i) * dp + ws + C, in.hl1[i]);
                 ld_vec<SD, B1X>(det + (hs + R + i) * dp + C, in.lh1[i]);
                 ld_vec<SD, B1X>(det + (hs + R + i) * dp + ws + C, in.hh1[i]);
@@ -514,7 +596,7 @@ __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_
         const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
 #pragma unroll
         for (int i = 0; i < B2Y; ++i) {
-            if constexpr (FULL) {
+            if (inb) {
                 ld_vec<SD, B2X>(det + (R + i) * dp + ws + C, in.hl2[i]);
                 ld_vec<SD, B2X>(det + (hs + R + i) * dp + C, in.lh2[i]);
                 ld_vec<SD, B2X>(det + (hs + R + i) * dp + ws + C, in.hh2[i]);
@@ -548,6 +630,7 @@ __device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_
     const int lr0 = rg * RY, lc0 = cg * RX;
     const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
     const int th2 = (th + 3) >> 2, tw2 = (tw + 3) >> 2;
+    const bool inb = FULL || (lr0 + RY <= th && lc0 + RX <= tw);   // whole block inside
 
     const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
     typename SX::raw* dst =
@@ -661,7 +744,7 @@ __device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_
         const int64_t R = (r0 >> 1) + (lr0 >> 1), C = (c0 >> 1) + (lc0 >> 1);
 #pragma unroll
         for (int i = 0; i < B1Y; ++i) {
-            if constexpr (FULL) {
+            if (inb) {
                 ld_vec<SL, B1X>(llp + (R + i) * lp + C, ll1[i]);
             } else {
 #pragma unroll
@@ -683,7 +766,7 @@ __device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_
             syn_edge(ll1[i][k], hl1[i][k], lh1[i][k], hh1[i][k], r1, c1, v[2 * i][2 * k],
                      v[2 * i][2 * k + 1], v[2 * i + 1][2 * k], v[2 * i + 1][2 * k + 1]);
         }
-    if constexpr (FULL) {
+    if (inb) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) st_vec<SX, RX>(dst + (int64_t)(lr0 + r) * p.dst_pitch + lc0, v[r]);
     } else {

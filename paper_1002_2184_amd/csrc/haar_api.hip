@@ -120,19 +120,11 @@ static void tile_grid(Pass2D& p, const Tile2D& tc) {
 // Launch-wide condition of the vector path.  Region rows are read/written in
 // 16-byte vectors; level-1/2 band rows and (for 1-2 level passes) the LL rows
 // in vectors of B1X / B2X elements (RX = 16 / region element bytes).
-static int vec_ok_2d(const Pass2D& p, bool inverse, int ebx, int ebl) {
+// Full tiles use vector accesses, which need only element alignment of every
+// pointer (sizes, pitches and band origins may be anything).
+static int vec_ok_2d(const Pass2D& p, bool inverse, int ebx, int ebd, int ebl) {
     const void* region = inverse ? (const void*)p.dst : p.src;
-    const int64_t rp = inverse ? p.dst_pitch : p.src_pitch;
-    const int64_t rb = inverse ? p.dst_bstride : p.src_bstride;
-    const int64_t b1x = (16 / ebx) / 2, b2x = (16 / ebx) / 4;
-    bool ok = aligned(region, 16) && (rp * ebx) % 16 == 0 && (rb * ebx) % 16 == 0;
-    ok = ok && aligned(p.det, 16) && p.det_pitch % b1x == 0 && p.det_bstride % b1x == 0;
-    const int64_t ws1 = (p.w + 1) >> 1, ws2 = (p.w + 3) >> 2;
-    ok = ok && ws1 % b1x == 0 && ws2 % b2x == 0;
-    if (p.levels <= 2)   // the approximation is stored / loaded from registers
-        ok = ok && aligned(p.ll, 16) && p.ll_pitch % b1x == 0 && p.ll_bstride % b1x == 0 &&
-             ((int64_t)ebl * b1x) <= 16;
-    return ok ? 1 : 0;
+    return aligned(region, ebx) && aligned(p.det, ebd) && aligned(p.ll, ebl) ? 1 : 0;
 }
 
 int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch, int dtype,
@@ -187,7 +179,7 @@ int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch
         tile_grid(p, tc);
         p.remap = tc.remap;
         p.persist = tc.wg_per_cu > 0 ? (int64_t)tc.wg_per_cu * device_cus() : 0;
-        p.vec_ok = vec_ok_2d(p, inverse, ebx, ebl);
+        p.vec_ok = vec_ok_2d(p, inverse, ebx, eb, ebl);
         hipError_t e = inverse ? launch_inv2d(p, dtype, pcfg, x_f32, ll_f32, s)
                                : launch_fwd2d(p, dtype, pcfg, x_f32, ll_f32, s);
         if (e != hipSuccess) rc = hip_error(e, inverse ? "inv2d launch" : "fwd2d launch");
@@ -226,18 +218,10 @@ static std::vector<Region1D> passes_1d(int64_t n, int L, int depth) {
 
 // Launch-wide condition of the vector path: 16-byte region accesses and, per
 // in-register level, detail spans of min(E >> lev, 16 / ebd) elements.
-static int vec_ok_1d(const Pass1D& p, bool inverse, int ebx, int ebd, const Chunk1D& cc) {
+// Full chunks use vector accesses, which need only element alignment.
+static int vec_ok_1d(const Pass1D& p, bool inverse, int ebx, int ebd, int ebl) {
     const void* region = inverse ? (const void*)p.dst : p.src;
-    const int64_t rb = inverse ? p.dst_bstride : p.src_bstride;
-    bool ok = aligned(region, 16) && (rb * ebx) % 16 == 0 && aligned(p.det, 16);
-    const int loge = log2_int(cc.ept);
-    for (int lev = 1; lev <= loge && lev <= p.levels; ++lev) {
-        const int cnt = cc.ept >> lev;
-        const int v = cnt < 16 / ebd ? cnt : 16 / ebd;
-        const int64_t ns = (p.n + ((int64_t)1 << lev) - 1) >> lev;
-        ok = ok && ns % v == 0 && p.det_bstride % v == 0;
-    }
-    return ok ? 1 : 0;
+    return aligned(region, ebx) && aligned(p.det, ebd) && aligned(p.ll, ebl) ? 1 : 0;
 }
 
 // One chunk pass over every item (levels <= on-chip depth), shared by the
@@ -282,7 +266,7 @@ int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype
             p.ll = a32;
             p.ll_bstride = m;
         }
-        p.vec_ok = vec_ok_1d(p, false, eb, a32 ? 4 : eb, cc);
+        p.vec_ok = vec_ok_1d(p, false, eb, eb, a32 ? 4 : eb);
         hipError_t e = launch_fwd1d(p, dtype, cfg, false, a32 != nullptr, s);
         if (e == hipSuccess) e = launch_finish1d(p, dtype, depth, L, a32 != nullptr, s);
         int rc = e == hipSuccess ? HAAR_OK : hip_error(e, "fwd1d launch");
@@ -295,7 +279,7 @@ int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype
     if (L > depth && inverse && L - depth <= kMaxWalkHost) {
         Pass1D p = chunk_pass(in, out, N, depth, batch, true, cc);
         p.levels_total = L;
-        p.vec_ok = vec_ok_1d(p, true, eb, eb, cc);
+        p.vec_ok = vec_ok_1d(p, true, eb, eb, eb);
         hipError_t e = launch_inv1d_walk(p, dtype, cfg, s);
         return e == hipSuccess ? HAAR_OK : hip_error(e, "inv1d launch");
     }
@@ -333,7 +317,7 @@ int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype
         p.remap = cc.remap;
         p.chunks_per_item = (r.n + cc.chunk() - 1) / cc.chunk();
         p.total_chunks = p.chunks_per_item * batch;
-        p.vec_ok = vec_ok_1d(p, inverse, ebx, eb, cc);
+        p.vec_ok = vec_ok_1d(p, inverse, ebx, eb, ll_f32 ? 4 : eb);
         hipError_t e = inverse ? launch_inv1d(p, dtype, cfg, x_f32, ll_f32, s)
                                : launch_fwd1d(p, dtype, cfg, x_f32, ll_f32, s);
         if (e != hipSuccess) rc = hip_error(e, inverse ? "inv1d launch" : "fwd1d launch");

@@ -147,10 +147,16 @@ struct StF16 {
 #define HAAR_NT_LOADS 0
 #endif
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef float v2f __attribute__((ext_vector_type(2)));
-typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+// Vector accesses assume only the alignment of the element type: rows and
+// band origins of arbitrary sizes start at any element.  On gfx9 and later
+// under ROCm the memory system runs in unaligned-access mode, so these stay
+// single 8- or 16-byte instructions whatever the address (a misaligned one
+// touches one more cache line).
+typedef float v4f __attribute__((ext_vector_type(4), aligned(4)));
+typedef float v2f __attribute__((ext_vector_type(2), aligned(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4), aligned(2)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2), aligned(2)));
+typedef unsigned int u32e __attribute__((aligned(2)));
 
 template <class T>
 __device__ __forceinline__ T ld_any(const T* p) {
@@ -166,8 +172,8 @@ __device__ __forceinline__ void st_any(T v, T* p) {
     __builtin_nontemporal_store(v, p);
 }
 
-// Load N consecutive elements (N * kBytes in {2, 4, 8, 16}, pointer aligned
-// to that size) into floats.
+// Load N consecutive elements (N * kBytes in {2, 4, 8, 16}; the pointer
+// needs only element alignment) into floats.
 template <class S, int N>
 __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
     constexpr int B = N * S::kBytes;
@@ -191,7 +197,7 @@ __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
             const v2u v = ld_any(reinterpret_cast<const v2u*>(p));
             w[0] = v.x; w[1] = v.y;
         } else if constexpr (B == 4) {
-            w[0] = ld_any(reinterpret_cast<const uint32_t*>(p));
+            w[0] = ld_any(reinterpret_cast<const u32e*>(p));
         } else {
             out[0] = S::ld(ld_any(p));
             return;
@@ -233,7 +239,7 @@ __device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {
                 v2u o = {w[0], w[1]};
                 st_any(o, reinterpret_cast<v2u*>(p));
             } else {
-                st_any(w[0], reinterpret_cast<uint32_t*>(p));
+                st_any((u32e)w[0], reinterpret_cast<u32e*>(p));
             }
         }
     }
@@ -241,6 +247,12 @@ __device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {
 
 template <class S>
 __device__ __forceinline__ void st1(typename S::raw* p, float v) { st_any(S::st(v), p); }
+
+// Ordinary (write-back) store of one element.  Used for the short row pieces
+// of the deepest 2D levels: these cover only part of a cache line each, and
+// partial lines cost less through the caches than streamed.
+template <class S>
+__device__ __forceinline__ void st1_cached(typename S::raw* p, float v) { *p = S::st(v); }
 
 template <class S>
 __device__ __forceinline__ float ld1(const typename S::raw* p) { return S::ld(ld_any(p)); }

@@ -44,6 +44,7 @@ struct Tile2D {
     int ry, rx, gy, gx;
     int remap;
     int wg_per_cu;                          // persistent interior grid: work-groups per CU
+    int map;                                // 1: wavefront-local analysis thread map
     int th() const { return gy * ry; }
     int tw() const { return gx * rx; }
     int threads() const { return gy * gx; }

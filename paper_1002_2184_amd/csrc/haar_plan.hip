@@ -362,13 +362,8 @@ int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype,
         pi.h = it.height;
         pi.w = it.width;
         pi.levels = it.levels;
-        // vector path: 16-byte rows and aligned level-1/2 band origins
-        const int rx = 16 / eb;
-        const int64_t b1x = rx / 2, b2x = rx / 4;
-        const void* region = inverse ? it.out : it.in;
-        const void* coef = inverse ? it.in : it.out;
-        bool ok = aligned(region, 16) && aligned(coef, 16) && (it.width * eb) % 16 == 0;
-        ok = ok && it.width % b1x == 0 && ((it.width + 1) / 2) % b1x == 0 && ((it.width + 3) / 4) % b2x == 0;
+        // vector path: needs element-aligned pointers only
+        const bool ok = aligned(it.in, eb) && aligned(it.out, eb);
         pi.vec_ok = ok ? 1 : 0;
         pl->items2.push_back(pi);
         for (int c = 0; c < kPlanCfgs2D; ++c) {
@@ -443,13 +438,7 @@ int haar_plan_create_1d(const haar_item_1d* items, int64_t count, int32_t dtype,
         pi.levels = it.levels;
         pi.chunk_levels = std::min(it.levels, kPlanLogC1);
         pi.nchunks = (int32_t)((it.length + kPlanC1 - 1) / kPlanC1);
-        const void* region = inverse ? it.out : it.in;
-        bool ok = aligned(region, 16) && aligned(it.in, 16) && aligned(it.out, 16);
-        for (int lev = 1; lev <= 4 && lev <= pi.chunk_levels; ++lev) {
-            const int cnt = kPlanE1 >> lev;
-            const int v = cnt < 16 / eb ? cnt : 16 / eb;
-            ok = ok && ceil_shift_host(it.length, lev) % v == 0;
-        }
+        const bool ok = aligned(it.in, eb) && aligned(it.out, eb);   // vector path: element alignment
         pi.vec_ok = ok ? 1 : 0;
         pi.a32 = -1;
         if (pi.levels > pi.chunk_levels) {

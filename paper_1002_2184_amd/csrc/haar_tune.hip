@@ -128,8 +128,9 @@ const char* haar_tune_candidate_name(int32_t dtype, int32_t index) {
     const Tile2D t = tile_config_2d(elem_bytes(dtype), index);
     char pers[32] = "";
     if (t.wg_per_cu > 0) snprintf(pers, sizeof pers, ", persistent %d/CU", t.wg_per_cu);
-    snprintf(buf, sizeof buf, "tile %dx%d, %d threads, %dx%d per thread%s%s", t.th(), t.tw(),
-             t.threads(), t.ry, t.rx, t.remap ? ", XCD-contiguous" : "", pers);
+    snprintf(buf, sizeof buf, "tile %dx%d, %d threads, %dx%d per thread%s%s%s", t.th(), t.tw(),
+             t.threads(), t.ry, t.rx, t.remap ? ", XCD-contiguous" : "", pers,
+             t.map ? ", wavefront-local analysis" : "");
     return buf;
 }
 

@@ -10,9 +10,11 @@ from workloads import generators as G
 pytestmark = pytest.mark.gpu
 
 DTYPES = [G.F32, G.BF16, G.F16]
-# (h, w): degenerate, single tile, multi-tile full, ragged, unaligned rows
+# (h, w): degenerate, single tile, multi-tile full, ragged, unaligned rows; full
+# tiles whose rows and band origins start at odd elements (W/2 or W/4 odd)
 SHAPES = [(1, 1), (1, 9), (7, 1), (2, 2), (3, 5), (32, 32), (32, 128), (64, 256), (33, 129),
-          (100, 102), (130, 70), (257, 300), (96, 520)]
+          (100, 102), (130, 70), (257, 300), (96, 520), (64, 1090), (96, 1546), (64, 1025),
+          (160, 578)]
 
 
 def _levels_for(h, w):
@@ -126,23 +128,35 @@ def test_offset_views_unaligned(T):
     check_signal(y.cpu().numpy().astype(np.float64), ref, rms(ref), G.F32, "offset fwd")
 
 
-def test_tile_configs_agree(T):
-    """Every tile shape gives the same result within the FP32 gate."""
+@pytest.mark.parametrize("dt", [G.F32, G.BF16])
+def test_tile_configs_agree(T, dt):
+    """Every tile shape (and thread map) gives the oracle's result at every
+    depth of one pass, on shapes with interior and edge tiles."""
     from paper_1002_2184_amd import _abi
-    xs = _input(G.F32, 2, 200, 330, 5)
-    xw = G.widen(xs, G.F32)
-    ref = oracle.fwd_2d(xw, 5)
+    cases = []
+    for shape in ((2, 200, 330), (1, 256, 1024)):
+        xs = _input(dt, *shape, 5)
+        xw = G.widen(xs, dt)
+        for L in (1, 2, 3, 4, 5):
+            ref = oracle.fwd_2d(xw, L)
+            cs = G.to_storage(ref, dt)
+            cases.append((shape, L, xs, xw, ref, cs, oracle.inv_2d(G.widen(cs, dt), L)))
     try:
-        for c in range(_abi.haar_tune_candidates_2d(0)):
-            assert _abi.haar_force_config_2d(0, c) == 0
-            y = G.widen(to_host(T.fwd2d(to_device(xs, G.F32), 5), G.F32), G.F32)
-            for b in range(2):
-                check_signal(y[b], ref[b], rms(xw[b]), G.F32, f"config {c}")
-            xr = G.widen(to_host(T.inv2d(to_device(G.to_storage(ref, G.F32), G.F32), 5), G.F32), G.F32)
-            for b in range(2):
-                check_signal(xr[b], xw[b], rms(xw[b]), G.F32, f"config {c} inv")
+        for c in range(_abi.haar_tune_candidates_2d(dt)):
+            assert _abi.haar_force_config_2d(dt, c) == 0
+            for shape, L, xs, xw, ref, cs, xref in cases:
+                y = G.widen(to_host(T.fwd2d(to_device(xs, dt), L), dt), dt)
+                xr = G.widen(to_host(T.inv2d(to_device(cs, dt), L), dt), dt)
+                for b in range(shape[0]):
+                    what = f"config {c} {shape} L={L} item {b}"
+                    if dt == G.F32:
+                        check_signal(y[b], ref[b], rms(xw[b]), dt, what)
+                        check_signal(xr[b], xref[b], rms(xw[b]), dt, what + " inv")
+                    else:
+                        check_lowp_coeffs(y[b], ref[b], rms(xw[b]), dt, band_views(shape[1:], L), what)
+                        check_lowp_signal(xr[b], xref[b], rms(xw[b]), dt, what + " inv")
     finally:
-        _abi.haar_force_config_2d(0, -1)
+        _abi.haar_force_config_2d(dt, -1)
 
 
 def test_config2_full_size():
