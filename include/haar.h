@@ -130,10 +130,13 @@ int haar_max_levels_2d(int64_t height, int64_t width);
  *
  * A plan lists the work units of all items (2D: tiles, 1D: chunks of 4096
  * samples), largest items first, and haar_plan_execute() enqueues ONE
- * persistent kernel whose work-groups claim units with an atomic counter
- * until the list is exhausted (a 1D analysis plan with items deeper than 12
+ * persistent kernel (grid = resident work-groups of the device) that drains
+ * the list.  1D plans default to a strided walk (work-group b takes units
+ * b, b + G, b + 2G, ...: the chunks are uniform); 2D plans default to
+ * claiming units with an atomic counter (edge tiles differ in cost).  See
+ * haar_plan_set_config.  A 1D analysis plan with items deeper than 12
  * levels enqueues a second, small kernel that finishes those items, one
- * work-group per item).  The plan itself holds host memory only; the
+ * work-group per item.  The plan itself holds host memory only; the
  * device-side tables and counters live in a caller-owned workspace of
  * haar_plan_workspace_size() bytes (256-byte aligned).
  *
@@ -179,12 +182,18 @@ int haar_plan_upload(haar_plan* plan, void* workspace, void* stream);
 int haar_plan_execute(const haar_plan* plan, void* workspace, void* stream);
 /* Number of work units and the persistent grid size (work-groups). */
 int haar_plan_info(const haar_plan* plan, int64_t* tiles, int32_t* grid);
-/* Select the tile shape of a 2D plan (0: 32 rows x 16 vectors, 1: 32 rows x
- * 32 vectors; 1D plans accept 0 only); the plan must be uploaded again. */
+/* Select a plan configuration; the plan must be uploaded again.  The
+ * schedule is 0: work-group b runs units b, b + G, b + 2G, ... of the list
+ * (1D default), or 1: work-groups claim units from an atomic counter (2D
+ * default).
+ * 2D: config = tile shape + 2 * schedule, tile shape 0: 32 rows x 16
+ * vectors, 1: 32 rows x 32 vectors (configs 0..3).  1D: config = schedule
+ * (0, 1). */
 int haar_plan_set_config(haar_plan* plan, int32_t config);
-/* Autotune a plan: time executes of every tile shape on `stream` (hipEvents;
- * synchronises the stream; overwrites the items' outputs), keep the fastest,
- * upload it, and return its index in *choice.  Not during capture. */
+/* Autotune a plan: time executes of every configuration on `stream`
+ * (hipEvents; synchronises the stream; overwrites the items' outputs), keep
+ * the fastest, upload it, and return its index in *choice.  Not during
+ * capture. */
 int haar_plan_tune(haar_plan* plan, void* workspace, void* stream, int32_t* choice);
 int haar_plan_destroy(haar_plan* plan);
 

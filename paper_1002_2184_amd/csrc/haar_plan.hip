@@ -81,7 +81,29 @@ __device__ __forceinline__ void retire(unsigned* ctr) {
 // ---------------------------------------------------------------------------
 // 2D
 // ---------------------------------------------------------------------------
-template <class S, int GY, int GX, bool INV>
+// Work-list walk of a plan kernel.  DYN: work-groups claim units with the
+// atomic counter (balances units of very different cost); otherwise unit
+// b, b + G, b + 2G, ... (no atomics; the units of a plan are nearly uniform
+// and sorted largest item first).  The unit index is made wavefront-uniform
+// so that the descriptors come through the scalar cache.
+template <bool DYN, class F>
+__device__ __forceinline__ void walk_units(unsigned n, unsigned* ctr, unsigned* s_slot, F&& body) {
+    if constexpr (DYN) {
+        unsigned unit;
+        while (claim(ctr, s_slot, n, unit)) {
+            body((unsigned)__builtin_amdgcn_readfirstlane((int)unit));
+            __syncthreads();   // LDS reuse by the next unit
+        }
+        retire(ctr);
+    } else {
+        for (unsigned unit = blockIdx.x; unit < n; unit += gridDim.x) {
+            body(unit);
+            __syncthreads();
+        }
+    }
+}
+
+template <class S, int GY, int GX, bool INV, bool DYN>
 __global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __restrict__ items,
                                                         const PlanTile2D* __restrict__ tiles,
                                                         unsigned ntiles, unsigned* ctr) {
@@ -90,8 +112,7 @@ __global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __rest
     constexpr int SM_FWD = G::SMEM, SM_INV = G::AN + G::BN + G::QPT * G::NT;
     __shared__ float sm[SM_FWD > SM_INV ? SM_FWD : SM_INV];
     __shared__ unsigned s_slot;
-    unsigned unit;
-    while (claim(ctr, &s_slot, ntiles, unit)) {
+    walk_units<DYN>(ntiles, ctr, &s_slot, [&](unsigned unit) {
         const PlanTile2D d = tiles[unit];
         const PlanItem2D it = items[d.item];
         Pass2D p{};
@@ -133,15 +154,13 @@ __global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __rest
                 inv2d_body<S, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in, sm);
             }
         }
-        __syncthreads();   // LDS reuse by the next unit
-    }
-    retire(ctr);
+    });
 }
 
 // ---------------------------------------------------------------------------
 // 1D
 // ---------------------------------------------------------------------------
-template <class S, bool INV>
+template <class S, bool INV, bool DYN>
 __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __restrict__ items,
                                                          const PlanChunk1D* __restrict__ chunks,
                                                          unsigned nunits, unsigned* ctr, float* a32) {
@@ -149,8 +168,7 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
     __shared__ df smd[NW];
     __shared__ float smf[NW * 8];
     __shared__ unsigned s_slot;
-    unsigned unit;
-    while (claim(ctr, &s_slot, nunits, unit)) {
+    walk_units<DYN>(nunits, ctr, &s_slot, [&](unsigned unit) {
         const PlanChunk1D d = chunks[unit];
         const PlanItem1D it = items[d.item];
         Pass1D p{};
@@ -190,9 +208,7 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
             else
                 inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smf, deep, top);
         }
-        __syncthreads();
-    }
-    retire(ctr);
+    });
 }
 
 // Second kernel of a 1D analysis plan: the levels beyond 12 of each deep
@@ -223,6 +239,7 @@ struct haar_plan {
     int dtype = 0;
     int inverse = 0;
     int cfg = 1;                       // 2D tile configuration (0: 32 rows x 16 vectors, 1: x 32)
+    int sched = 0;                     // 0: strided work-list walk, 1: atomic claiming (2D default)
     std::vector<PlanItem2D> items2;
     std::vector<PlanTile2D> tiles2[2];  // per tile configuration
     std::vector<PlanItem1D> items1;
@@ -269,9 +286,13 @@ hipError_t launch_plan2d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
         hipLaunchKernelGGL(kernel, dim3(g), dim3(threads), 0, s, items, tiles, n, ctr);
         return hipGetLastError();
     };
-    if (pl->cfg == 0)
-        return pl->inverse ? go(plan2d_kernel<S, 8, 32, true>, 256) : go(plan2d_kernel<S, 8, 32, false>, 256);
-    return pl->inverse ? go(plan2d_kernel<S, 8, 64, true>, 512) : go(plan2d_kernel<S, 8, 64, false>, 512);
+    const bool inv = pl->inverse != 0, dyn = pl->sched != 0;
+    if (pl->cfg == 0) {
+        if (dyn) return inv ? go(plan2d_kernel<S, 8, 32, true, true>, 256) : go(plan2d_kernel<S, 8, 32, false, true>, 256);
+        return inv ? go(plan2d_kernel<S, 8, 32, true, false>, 256) : go(plan2d_kernel<S, 8, 32, false, false>, 256);
+    }
+    if (dyn) return inv ? go(plan2d_kernel<S, 8, 64, true, true>, 512) : go(plan2d_kernel<S, 8, 64, false, true>, 512);
+    return inv ? go(plan2d_kernel<S, 8, 64, true, false>, 512) : go(plan2d_kernel<S, 8, 64, false, false>, 512);
 }
 
 template <class S>
@@ -288,8 +309,9 @@ hipError_t launch_plan1d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
         hipLaunchKernelGGL(kernel, dim3(g), dim3(kPlanNT1), 0, s, items, chunks, n, ctr, a32);
         return hipGetLastError();
     };
-    if (pl->inverse) return go(plan1d_kernel<S, true>);
-    hipError_t e = go(plan1d_kernel<S, false>);
+    const bool dyn = pl->sched != 0;
+    if (pl->inverse) return dyn ? go(plan1d_kernel<S, true, true>) : go(plan1d_kernel<S, true, false>);
+    hipError_t e = dyn ? go(plan1d_kernel<S, false, true>) : go(plan1d_kernel<S, false, false>);
     if (e != hipSuccess || query_only || pl->deep1.empty()) return e;
     const int32_t* deep = (const int32_t*)((char*)ws + pl->off_deep);
     const unsigned nd = (unsigned)pl->deep1.size();
@@ -310,6 +332,12 @@ hipError_t launch_plan(const haar_plan* pl, void* ws, hipStream_t s, bool query_
         case 1: return launch_plan1d<StBF16>(pl, ws, s, query_only, grid);
         default: return launch_plan1d<StF16>(pl, ws, s, query_only, grid);
     }
+}
+
+// Plan configurations: 2D, tile shape + 2 * schedule (0..3); 1D, the schedule (0, 1).
+int plan_configs(const haar_plan* pl) { return pl->dim == 2 ? 2 * kPlanCfgs2D : 2; }
+int plan_config_index(const haar_plan* pl) {
+    return pl->dim == 2 ? pl->cfg + kPlanCfgs2D * pl->sched : pl->sched;
 }
 
 void layout(haar_plan* pl, size_t item_bytes, size_t nitems, size_t unit_bytes, int64_t nunits,
@@ -383,6 +411,7 @@ int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype,
     const int c = choose_config_2d(dtype, inverse != 0, items[order[0]].height, items[order[0]].width,
                                    items[order[0]].levels);
     pl->cfg = tile_config_2d(eb, c).gx == 32 ? 0 : 1;
+    pl->sched = 1;   // 2D tiles differ in cost (edge tiles): claim them
     layout(pl, sizeof(PlanItem2D), pl->items2.size(), sizeof(PlanTile2D),
            (int64_t)std::max(pl->tiles2[0].size(), pl->tiles2[1].size()), 2);
     pl->nunits = (int64_t)pl->tiles2[pl->cfg].size();
@@ -517,12 +546,16 @@ int haar_plan_info(const haar_plan* plan, int64_t* tiles, int32_t* grid) {
 
 int haar_plan_set_config(haar_plan* plan, int32_t config) {
     if (!plan) return set_error(HAAR_ERR_PLAN, "plan is NULL");
-    if (plan->dim != 2) return config == 0 ? HAAR_OK : set_error(HAAR_ERR_UNSUPPORTED, "1D plans have one chunk shape");
-    if (config < 0 || config >= kPlanCfgs2D)
-        return set_error(HAAR_ERR_UNSUPPORTED, "plan tile configuration %d not available", config);
-    plan->cfg = config;
-    plan->nunits = (int64_t)plan->tiles2[config].size();
-    plan->uploaded = false;          // the work-list changed: upload again
+    if (config < 0 || config >= plan_configs(plan))
+        return set_error(HAAR_ERR_UNSUPPORTED, "plan configuration %d not available", config);
+    if (plan->dim == 2) {
+        plan->cfg = config % kPlanCfgs2D;
+        plan->sched = config / kPlanCfgs2D;
+        plan->nunits = (int64_t)plan->tiles2[plan->cfg].size();
+    } else {
+        plan->sched = config;
+    }
+    plan->uploaded = false;          // the work-list may have changed: upload again
     plan->uploaded_to = nullptr;
     return HAAR_OK;
 }
@@ -531,14 +564,14 @@ int haar_plan_tune(haar_plan* plan, void* workspace, void* stream, int32_t* choi
     if (!plan) return set_error(HAAR_ERR_PLAN, "plan is NULL");
     if (!workspace || !choice) return set_error(HAAR_ERR_NULL, "workspace or choice is NULL");
     hipStream_t s = (hipStream_t)stream;
-    const int ncfg = plan->dim == 2 ? kPlanCfgs2D : 1;
+    const int ncfg = plan_configs(plan);
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return set_error(HAAR_ERR_HIP, "hipEventCreate");
     if (hipEventCreate(&b) != hipSuccess) {
         (void)hipEventDestroy(a);
         return set_error(HAAR_ERR_HIP, "hipEventCreate");
     }
-    int best = plan->cfg, rc = HAAR_OK;
+    int best = plan_config_index(plan), rc = HAAR_OK;
     float best_ms = 1e30f;
     for (int c = 0; c < ncfg && rc == HAAR_OK; ++c) {
         if ((rc = haar_plan_set_config(plan, c)) != HAAR_OK) break;

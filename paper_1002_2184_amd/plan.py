@@ -39,7 +39,7 @@ class _Plan:
         _abi.check(_abi.haar_plan_execute(self._ptr, self.workspace.data_ptr(), self._stream()))
 
     def tune(self) -> int:
-        """Time the plan's tile shapes (overwrites the outputs) and keep the fastest."""
+        """Time the plan's configurations (overwrites the outputs) and keep the fastest."""
         choice = ctypes.c_int32(-1)
         _abi.check(_abi.haar_plan_tune(self._ptr, self.workspace.data_ptr(), self._stream(),
                                        ctypes.byref(choice)))

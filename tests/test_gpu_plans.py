@@ -72,14 +72,14 @@ def test_plan2d_configs_and_tune(P):
     lv = _lv(SHAPES_2D, 4)
     plan = P.Plan2D(xd, yd, lv)
     refs = [oracle.fwd_2d(x.astype(np.float64), L) for x, L in zip(xs, lv)]
-    for cfg in (0, 1):
+    for cfg in (0, 1, 2, 3):          # tile shape + 2 * schedule (strided, atomic claiming)
         plan.set_config(cfg)
         plan.execute()
         torch.cuda.synchronize()
         for y, r, x in zip(yd, refs, xs):
             check_signal(to_host(y, G.F32).astype(np.float64), r, rms(x), G.F32, f"config {cfg}")
     choice = plan.tune()
-    assert choice in (0, 1)
+    assert choice in (0, 1, 2, 3)
     plan.execute()
     torch.cuda.synchronize()
     for y, r, x in zip(yd, refs, xs):
@@ -134,6 +134,37 @@ def test_plan1d_full_depth_matches_oracle(P, dt):
                          f"plan1d inv n={c.size} rep {rep}")
 
 
+def test_plan1d_schedules(P):
+    """Both work-list schedules (strided, atomic claiming) give the oracle's
+    result, executed twice each (the claiming counters reset themselves)."""
+    import torch
+    lengths = [1 << 16, 5000, 4096, 70000, 777]
+    levels = [16, 13, 12, 14, 10]
+    xs = _sigs(G.F32, lengths, seed=19)
+    xd = [to_device(x, G.F32) for x in xs]
+    yd = [torch.empty_like(x) for x in xd]
+    plan = P.Plan1D(xd, yd, levels)
+    refs = [oracle.fwd_1d(x.astype(np.float64), L) for x, L in zip(xs, levels)]
+    cs = [to_device(G.to_storage(r, G.F32), G.F32) for r in refs]
+    zd = [torch.empty_like(c) for c in cs]
+    iplan = P.Plan1D(cs, zd, levels, inverse=True)
+    for sched in (0, 1, 0):
+        plan.set_config(sched)
+        iplan.set_config(sched)
+        for rep in range(2):
+            for y in yd + zd:
+                y.fill_(float("nan"))
+            plan.execute()
+            iplan.execute()
+            torch.cuda.synchronize()
+            for x, y, z, r, L in zip(xs, yd, zd, refs, levels):
+                what = f"schedule {sched} n={x.size} L={L} rep {rep}"
+                check_signal(to_host(y, G.F32).astype(np.float64), r, rms(x), G.F32, what)
+                xref = oracle.inv_1d(G.widen(G.to_storage(r, G.F32), G.F32), L)
+                check_signal(to_host(z, G.F32).astype(np.float64), xref, rms(x), G.F32, what + " inv")
+    assert plan.tune() in (0, 1)
+
+
 def test_plan1d_partial_levels(P):
     import torch
     lengths = [50000, 4096, 123, 70000]
@@ -158,6 +189,8 @@ def test_plan_graph_replay(P):
     ys1 = [torch.empty_like(x) for x in xs1]
     p2 = P.Plan2D(xs2, ys2, _lv(SHAPES_2D[:5], 5))
     p1 = P.Plan1D(xs1, ys1, [18, 13, 12])
+    p2.set_config(3)                  # atomic claiming: the counters must reset themselves
+    p1.set_config(1)
     p2.execute()
     p1.execute()
     torch.cuda.synchronize()
