@@ -67,6 +67,10 @@ class Oracle:
             fn = getattr(lib, name)
             fn.argtypes = [P, P, i64, i64, i32, i64]
             fn.restype = None
+        lib.oracle_shrink_1d.argtypes = [P, P, i64, i32, i64, i32, P]
+        lib.oracle_shrink_1d.restype = None
+        lib.oracle_shrink_2d.argtypes = [P, P, i64, i64, i32, i64, i32, P]
+        lib.oracle_shrink_2d.restype = None
         lib.oracle_filter_taps.argtypes = [P, P, P, P]
         lib.oracle_filter_taps.restype = None
         lib.oracle_num_threads.argtypes = []
@@ -118,6 +122,35 @@ class Oracle:
         """Separable multi-level 2D synthesis on the last two axes."""
         return self._call_2d("oracle_inv_2d", y, levels)
 
+    def _thresholds(self, levels, thresholds):
+        t = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float64).reshape(-1))
+        if t.size != int(levels):
+            raise ValueError(f"need one threshold per level ({levels}), got {t.size}")
+        return t
+
+    def shrink_1d(self, x, levels, mode, thresholds):
+        """Analysis, thresholding of every level-j detail with thresholds[j-1]
+        (mode 0 hard, 1 soft), synthesis; along the last axis."""
+        _check_levels(levels)
+        t = self._thresholds(levels, thresholds)
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        n = x.shape[-1]
+        y = np.empty_like(x)
+        self.lib.oracle_shrink_1d(_ptr(x), _ptr(y), n, int(levels), x.size // n, int(mode), _ptr(t))
+        return y
+
+    def shrink_2d(self, x, levels, mode, thresholds):
+        """2D analysis, thresholding of the level-j bands with thresholds[j-1]
+        (mode 0 hard, 1 soft), synthesis; on the last two axes."""
+        _check_levels(levels)
+        t = self._thresholds(levels, thresholds)
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        h, w = x.shape[-2], x.shape[-1]
+        y = np.empty_like(x)
+        self.lib.oracle_shrink_2d(_ptr(x), _ptr(y), h, w, int(levels), x.size // (h * w), int(mode),
+                                  _ptr(t))
+        return y
+
     def filter_taps(self):
         """(b0, b1, a0, a1), each a length-2 causal FIR tap array."""
         arrs = [np.zeros(2) for _ in range(4)]
@@ -163,6 +196,14 @@ def fwd_2d(x, levels: int) -> np.ndarray:
 
 def inv_2d(y, levels: int) -> np.ndarray:
     return default().inv_2d(y, levels)
+
+
+def shrink_1d(x, levels: int, mode: int, thresholds) -> np.ndarray:
+    return default().shrink_1d(x, levels, mode, thresholds)
+
+
+def shrink_2d(x, levels: int, mode: int, thresholds) -> np.ndarray:
+    return default().shrink_2d(x, levels, mode, thresholds)
 
 
 def filter_taps():

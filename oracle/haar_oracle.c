@@ -320,6 +320,65 @@ void oracle_inv_2d(const double* y, double* x, int64_t h, int64_t w,
         inv_2d_item(y + b * h * w, x + b * h * w, h, w, levels);
 }
 
+/* ---------------------------------------------------------------------- */
+/* Shrinkage of the detail coefficients between analysis and synthesis.   */
+/* The paper's applications (Sec. I: compression and analysis of signals  */
+/* and images; Sec. VI: biosignals and medical images) decompose, act on   */
+/* the coefficients and reconstruct.  Here the action is thresholding of   */
+/* every detail coefficient of level j with threshold thr[j-1]:            */
+/*   mode 0 (hard): keep d when |d| > t, else 0;                           */
+/*   mode 1 (soft): sign(d) * max(|d| - t, 0).                             */
+/* The approximation a_L (LL_L) is left unchanged.                          */
+/* ---------------------------------------------------------------------- */
+static double shrink_value(double d, int mode, double t)
+{
+    if (mode == 0) return fabs(d) > t ? d : 0.0;
+    const double m = fabs(d) - t;
+    if (m <= 0.0) return 0.0;
+    return d > 0.0 ? m : -m;
+}
+
+void oracle_shrink_1d(const double* x, double* y, int64_t n, int32_t levels,
+                      int64_t batch, int32_t mode, const double* thr)
+{
+    double* c = (double*)malloc((size_t)n * sizeof(double));
+    int64_t len[64];
+    len[0] = n;
+    for (int j = 1; j <= levels; ++j) len[j] = (len[j - 1] + 1) / 2;
+    for (int64_t b = 0; b < batch; ++b) {
+        oracle_fwd_1d(x + b * n, c, n, levels, 1);
+        for (int j = 1; j <= levels; ++j)            /* d_j = c[len[j], len[j-1]) */
+            for (int64_t i = len[j]; i < len[j - 1]; ++i)
+                c[i] = shrink_value(c[i], mode, thr[j - 1]);
+        oracle_inv_1d(c, y + b * n, n, levels, 1);
+    }
+    free(c);
+}
+
+void oracle_shrink_2d(const double* x, double* y, int64_t h, int64_t w,
+                      int32_t levels, int64_t batch, int32_t mode,
+                      const double* thr)
+{
+    double* c = (double*)malloc((size_t)(h * w) * sizeof(double));
+    int64_t lh[64], lw[64];
+    lh[0] = h; lw[0] = w;
+    for (int j = 1; j <= levels; ++j) {
+        lh[j] = (lh[j - 1] + 1) / 2;
+        lw[j] = (lw[j - 1] + 1) / 2;
+    }
+    for (int64_t b = 0; b < batch; ++b) {
+        fwd_2d_item(x + b * h * w, c, h, w, levels);
+        /* level j bands: the level-(j-1) LL region minus the level-j LL region */
+        for (int j = 1; j <= levels; ++j)
+            for (int64_t r = 0; r < lh[j - 1]; ++r)
+                for (int64_t q = 0; q < lw[j - 1]; ++q)
+                    if (r >= lh[j] || q >= lw[j])
+                        c[r * w + q] = shrink_value(c[r * w + q], mode, thr[j - 1]);
+        inv_2d_item(c, y + b * h * w, h, w, levels);
+    }
+    free(c);
+}
+
 /* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
 int oracle_num_threads(void)
 {

@@ -266,9 +266,112 @@ def pin_adjoint(orc):
         assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs)), "2D adjoint"
 
 
+# ---------------------------------------------------------------------------
+# Shrinkage (analysis, per-level thresholding of the details, synthesis)
+# ---------------------------------------------------------------------------
+def _shrink(c, mode, t):
+    if mode == 0:
+        return np.where(np.abs(c) > t, c, 0.0)
+    return np.sign(c) * np.maximum(np.abs(c) - t, 0.0)
+
+
+def _row_levels_1d(n, L):
+    """Level of every packed 1D coefficient (0 for the approximation a_L)."""
+    ns = sizes(n, L)
+    lev = np.zeros(n, dtype=int)
+    for j in range(1, L + 1):
+        lev[ns[j]:ns[j - 1]] = j
+    return lev
+
+
+def _row_levels_2d(h, w, L):
+    hs, ws = sizes(h, L), sizes(w, L)
+    lev = np.zeros((h, w), dtype=int)
+    for j in range(L, 0, -1):            # inside the level-(j-1) LL region, outside level j's
+        region = np.zeros((h, w), dtype=bool)
+        region[:hs[j - 1], :ws[j - 1]] = True
+        region[:hs[j], :ws[j]] = False
+        lev[region] = j
+    return lev.ravel()
+
+
+def _thresholds_away(coefs, lev, L, rng, margin=1e-6):
+    """Per-level thresholds drawn from the spread of each level's magnitudes,
+    moved off any coefficient magnitude so that the keep/zero decision is
+    unambiguous."""
+    t = np.zeros(L)
+    for j in range(1, L + 1):
+        mags = np.abs(coefs[lev == j])
+        while True:
+            cand = float(rng.uniform(0.0, 1.2) * (mags.max() if mags.size else 1.0))
+            if mags.size == 0 or np.min(np.abs(mags - cand)) > margin * max(cand, 1e-12):
+                t[j - 1] = cand
+                break
+    return t
+
+
+def pin_shrink_matrix(orc):
+    """shrink(x) = W^T S(W x) with W the closed-form transform matrix (any 1D
+    length, 2D sizes divisible by 2^L), S the per-level threshold rule."""
+    rng = np.random.default_rng(23)
+    for n, L in [(16, 4), (13, 3), (33, 5), (24, 2), (7, 3)]:
+        W = carry_matrix_1d(n, L)
+        lev = _row_levels_1d(n, L)
+        for mode in (0, 1):
+            x = rng.standard_normal(n)
+            c = W @ x
+            t = _thresholds_away(c, lev, L, rng)
+            tt = np.concatenate([[0.0], t])[lev]
+            want = W.T @ np.where(lev > 0, _shrink(c, mode, tt), c)
+            _close(orc.shrink_1d(x, L, mode, t), want, 1e-12, f"1D shrink n={n} L={L} mode {mode}")
+    for h, w, L in [(8, 8, 3), (4, 8, 2), (16, 8, 3)]:
+        W = haar_matrix_2d_dyadic(h, w, L)
+        lev = _row_levels_2d(h, w, L)
+        for mode in (0, 1):
+            x = rng.standard_normal((h, w))
+            c = W @ x.ravel()
+            t = _thresholds_away(c, lev, L, rng)
+            tt = np.concatenate([[0.0], t])[lev]
+            want = (W.T @ np.where(lev > 0, _shrink(c, mode, tt), c)).reshape(h, w)
+            _close(orc.shrink_2d(x, L, mode, t), want, 1e-12, f"2D shrink {h}x{w} L={L} mode {mode}")
+
+
+def pin_shrink_extremes(orc):
+    """Threshold 0 reconstructs the input; an infinite threshold leaves the
+    block means (every aligned 2^L block, or 2^L x 2^L block, replaced by its
+    mean, when 2^L divides the size)."""
+    rng = np.random.default_rng(29)
+    x = rng.standard_normal((2, 96))
+    for mode in (0, 1):
+        _close(orc.shrink_1d(x, 5, mode, np.zeros(5)), x, TOL, f"1D threshold 0 mode {mode}")
+        blocks = x.reshape(2, 96 // 32, 32).mean(axis=-1, keepdims=True)
+        want = np.broadcast_to(blocks, (2, 3, 32)).reshape(2, 96)
+        _close(orc.shrink_1d(x, 5, mode, np.full(5, 1e300)), want, TOL, f"1D block means mode {mode}")
+    x2 = rng.standard_normal((24, 40))
+    for mode in (0, 1):
+        _close(orc.shrink_2d(x2, 3, mode, np.zeros(3)), x2, TOL, f"2D threshold 0 mode {mode}")
+        m = x2.reshape(3, 8, 5, 8).mean(axis=(1, 3))
+        want = np.repeat(np.repeat(m, 8, axis=0), 8, axis=1)
+        _close(orc.shrink_2d(x2, 3, mode, np.full(3, 1e300)), want, TOL, f"2D block means mode {mode}")
+
+
+def pin_shrink_hard_projection(orc):
+    """Hard thresholding in an orthonormal basis is a projection: applying it
+    twice equals applying it once (odd sizes included)."""
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal((3, 101))
+    t = np.array([0.5, 0.8, 1.1, 0.3])
+    once = orc.shrink_1d(x, 4, 0, t)
+    _close(orc.shrink_1d(once, 4, 0, t), once, 1e-12, "1D hard twice")
+    x2 = rng.standard_normal((37, 29))
+    t2 = np.array([0.7, 1.0, 1.5])
+    once2 = orc.shrink_2d(x2, 3, 0, t2)
+    _close(orc.shrink_2d(once2, 3, 0, t2), once2, 1e-12, "2D hard twice")
+
+
 ALL_PINS = [
     pin_paper_coefficients, pin_worked_examples, pin_dyadic_closed_form, pin_carry_weights,
     pin_carry_impulse, pin_orthonormal_and_inverse, pin_direct_equals_fast, pin_alias_free_taps,
     pin_constant, pin_parseval_and_pr, pin_2d_separable, pin_2d_dyadic_closed_form,
-    pin_locality, pin_adjoint,
+    pin_locality, pin_adjoint, pin_shrink_matrix, pin_shrink_extremes, pin_shrink_hard_projection,
 ]

@@ -54,6 +54,11 @@ MUTANTS = {
                             "for (int j = 1; j <= levels; ++j) {\n        const int64_t cur = len[j - 1];\n        memcpy(tmp, x, (size_t)cur * sizeof(double));"),
     "direct_tap_sign": ("b1[0] = s;  b1[1] = -s;", "b1[0] = -s; b1[1] = s;"),
     "direct_wrong_phase": ("out[m] = y0[2 * m + 1];", "out[m] = y0[2 * m];"),
+    "shrink_threshold_level_order": ("c[i] = shrink_value(c[i], mode, thr[j - 1]);",
+                                     "c[i] = shrink_value(c[i], mode, thr[levels - j]);"),
+    "shrink_soft_sign": ("return d > 0.0 ? m : -m;", "return d > 0.0 ? -m : m;"),
+    "shrink_2d_ll_included": ("if (r >= lh[j] || q >= lw[j])", "if (r >= 0)"),
+    "shrink_2d_only_hh": ("if (r >= lh[j] || q >= lw[j])", "if (r >= lh[j] && q >= lw[j])"),
     "2d_row_skips_last": ("for (int64_t r = 0; r < ch; ++r) {            /* rows (width)   */",
                           "for (int64_t r = 0; r < ch - 1; ++r) {            /* rows (width)   */"),
 }
