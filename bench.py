@@ -288,6 +288,61 @@ def suite():
     res["unit_elements_per_s"] = "G elements/s, fwd + bwd"
     print(json.dumps(res), flush=True)
 
+    # 5) fused shrinkage (analysis -> soft threshold -> synthesis in one HBM
+    #    pass) on the 4096^2 image, 5 levels, 16 rotating sets; beside the
+    #    same pipeline unfused: fwd2d, torch elementwise threshold, inv2d
+    x0 = torch.from_numpy(G.config2()).to(dev)
+    sets = 16
+    xs = [x0.clone() for _ in range(sets)]
+    ys = [torch.empty_like(x0) for _ in range(sets)]
+    cs = [torch.empty_like(x0) for _ in range(sets)]
+    thr = [40.0, 20.0, 10.0, 5.0, 2.5]
+    kk = [0]
+
+    def fused():
+        k = kk[0] = (kk[0] + 1) % sets
+        T.shrink2d(xs[k], 5, thr, "soft", out=ys[k])
+
+    def unfused():
+        k = kk[0] = (kk[0] + 1) % sets
+        c = T.fwd2d(xs[k], 5, out=cs[k])
+        ll = c[:128, :128].clone()
+        c.copy_(torch.sign(c) * torch.clamp(c.abs() - thr[0], min=0.0))
+        c[:128, :128] = ll
+        T.inv2d(c, 5, out=ys[k])
+    ms_f = _timed(fused, 96, 16, st)
+    ms_u = _timed(unfused, 32, 8, st)
+    nb = 2 * x0.numel() * 4
+    print(json.dumps({"workload": "2d-smooth-4096x4096-L5 fused soft shrink",
+                      "us_fused": round(ms_f * 1e3, 2), "gbps_fused_one_pass": round(nb / (ms_f * 1e-3) / 1e9, 1),
+                      "us_unfused_fwd_threshold_inv": round(ms_u * 1e3, 2),
+                      "speedup_vs_unfused": round(ms_u / ms_f, 2)}), flush=True)
+    del xs, ys, cs, x0
+    torch.cuda.empty_cache()
+
+    # 6) the same in 1D: 256 signals of 65536 samples, 12 levels, one chunk pass
+    x1 = torch.randn(256, 65536, device=dev)
+    x1s = [x1.clone() for _ in range(4)]
+    y1s = [torch.empty_like(x1) for _ in range(4)]
+    kk[0] = 0
+
+    def fused1():
+        k = kk[0] = (kk[0] + 1) % 4
+        T.shrink1d(x1s[k], 12, 0.5, "soft", out=y1s[k])
+
+    def plain1():
+        k = kk[0] = (kk[0] + 1) % 4
+        T.fwd1d(x1s[k], 12, out=y1s[k])
+        T.inv1d(y1s[k], 12, out=x1s[(k + 2) % 4])
+    ms_f1 = _timed(fused1, 48, 8, st)
+    ms_p1 = _timed(plain1, 24, 4, st)
+    nb1 = 2 * x1.numel() * 4
+    print(json.dumps({"workload": "1d-256x65536-L12 fused soft shrink",
+                      "us_fused": round(ms_f1 * 1e3, 2),
+                      "gbps_fused_one_pass": round(nb1 / (ms_f1 * 1e-3) / 1e9, 1),
+                      "us_plain_fwd_inv": round(ms_p1 * 1e3, 2),
+                      "speedup_vs_fwd_inv": round(ms_p1 / ms_f1, 2)}), flush=True)
+
 
 def cpu_baseline(x_np, budget_s: float):
     """The FP64 oracle (fwd + inv of the same image) on this host's cores."""

@@ -87,7 +87,8 @@ typedef enum {
     HAAR_ERR_WORKSPACE = 6,   /* workspace NULL, too small or misaligned           */
     HAAR_ERR_HIP = 7,         /* a HIP runtime call failed (see haar_last_error)   */
     HAAR_ERR_PLAN = 8,        /* NULL / not uploaded plan, or an invalid plan item */
-    HAAR_ERR_UNSUPPORTED = 9  /* valid arguments this build does not implement     */
+    HAAR_ERR_UNSUPPORTED = 9, /* valid arguments this build does not implement     */
+    HAAR_ERR_ARG = 10         /* an argument value is invalid (mode, threshold)    */
 } haar_status;
 
 /* ------------------------------------------------------------------------
@@ -116,6 +117,43 @@ int haar_fwd_2d(const void* x, void* y, int64_t height, int64_t width,
  * haar_fwd_2d (columns, then rows, per level, from level L down to 1). */
 int haar_inv_2d(const void* y, void* x, int64_t height, int64_t width,
                 int32_t levels, int64_t batch, int32_t dtype, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Fused shrinkage: analysis, thresholding of the detail coefficients,
+ * synthesis, in ONE pass over HBM (each element is read once and written
+ * once, against three passes for haar_fwd_*, an elementwise step and
+ * haar_inv_*).  This is the decompose / act on the coefficients /
+ * reconstruct pipeline of the applications named in Sec. I (compression,
+ * signal and image analysis) and Sec. VI (biosignals, medical images).
+ *
+ * Every detail coefficient of level j (1D: d_j; 2D: HL_j, LH_j, HH_j) is
+ * replaced with
+ *   HAAR_SHRINK_HARD: d if |d| > t, else 0     (keep the large coefficients)
+ *   HAAR_SHRINK_SOFT: sign(d) * max(|d| - t, 0) (shrink every coefficient)
+ * with t = thresholds[j - 1]; the approximation a_L / LL_L is kept.  The
+ * coefficients stay in FP32 on chip between the analysis and the synthesis;
+ * only the output is rounded to the storage type.
+ *
+ * x, y: device pointers, [batch][length] or [batch][height][width], storage
+ * dtype, out-of-place (overlap returns HAAR_ERR_ALIAS).  thresholds: HOST
+ * array of `levels` floats, read during the call (may be NULL when levels
+ * is 0), each >= 0 (+inf allowed); a negative or NaN threshold or an unknown
+ * mode returns HAAR_ERR_ARG.  Fused depth: 1D levels <= 12 (one 4096-sample
+ * chunk per work-group), 2D levels <= 5 (one 32-row tile per work-group);
+ * deeper requests return HAAR_ERR_UNSUPPORTED.  levels = 0 copies.  The
+ * calls allocate nothing and never synchronise.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    HAAR_SHRINK_HARD = 0,
+    HAAR_SHRINK_SOFT = 1
+} haar_shrink_mode;
+
+int haar_shrink_1d(const void* x, void* y, int64_t length, int32_t levels,
+                   int64_t batch, int32_t dtype, int32_t mode,
+                   const float* thresholds, void* stream);
+int haar_shrink_2d(const void* x, void* y, int64_t height, int64_t width,
+                   int32_t levels, int64_t batch, int32_t dtype, int32_t mode,
+                   const float* thresholds, void* stream);
 
 /* ceil(log2(length)) for length >= 1 (0 for length 1); -1 if length < 1.
  * Beyond this depth every further level would be a no-op. */

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhaar.so")
 STATUS = {
     0: "HAAR_OK", 1: "HAAR_ERR_NULL", 2: "HAAR_ERR_DTYPE", 3: "HAAR_ERR_SHAPE",
     4: "HAAR_ERR_LEVELS", 5: "HAAR_ERR_ALIAS", 6: "HAAR_ERR_WORKSPACE", 7: "HAAR_ERR_HIP",
-    8: "HAAR_ERR_PLAN", 9: "HAAR_ERR_UNSUPPORTED",
+    8: "HAAR_ERR_PLAN", 9: "HAAR_ERR_UNSUPPORTED", 10: "HAAR_ERR_ARG",
 }
 
 
@@ -40,11 +40,14 @@ class Item2D(ctypes.Structure):
 _lib = None
 
 _VP, _I64, _I32, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+_FP = ctypes.POINTER(ctypes.c_float)
 _SIGS = {
     "haar_fwd_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_inv_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_fwd_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_inv_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
+    "haar_shrink_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _I32, _FP, _VP], ctypes.c_int),
+    "haar_shrink_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _I32, _FP, _VP], ctypes.c_int),
     "haar_max_levels_1d": ([_I64], ctypes.c_int),
     "haar_max_levels_2d": ([_I64, _I64], ctypes.c_int),
     "haar_plan_create_1d": ([ctypes.POINTER(Item1D), _I64, _I32, _I32, ctypes.POINTER(_VP)], ctypes.c_int),
@@ -109,6 +112,23 @@ def haar_fwd_2d(x, y, height, width, levels, batch, dtype, stream=0):
 
 def haar_inv_2d(y, x, height, width, levels, batch, dtype, stream=0):
     return lib().haar_inv_2d(y, x, height, width, levels, batch, dtype, stream)
+
+
+def haar_shrink_1d(x, y, length, levels, batch, dtype, mode, thresholds, stream=0):
+    """thresholds: a sequence of `levels` floats (copied into a host array)."""
+    return lib().haar_shrink_1d(x, y, length, levels, batch, dtype, mode, _floats(thresholds), stream)
+
+
+def haar_shrink_2d(x, y, height, width, levels, batch, dtype, mode, thresholds, stream=0):
+    return lib().haar_shrink_2d(x, y, height, width, levels, batch, dtype, mode, _floats(thresholds),
+                                stream)
+
+
+def _floats(values):
+    if values is None:
+        return None
+    vals = [float(v) for v in values]
+    return (ctypes.c_float * max(1, len(vals)))(*vals)
 
 
 def haar_max_levels_1d(length):

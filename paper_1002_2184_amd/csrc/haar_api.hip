@@ -395,6 +395,50 @@ int haar_inv_2d(const void* y, void* x, int64_t height, int64_t width, int32_t l
     return api_2d(y, x, height, width, levels, batch, dtype, stream, true);
 }
 
+// Fused shrinkage: the plain-call checks, then mode and thresholds (host
+// array, read during the call), then the fused depth.
+static int check_shrink(int32_t levels, int32_t mode, const float* thresholds, int max_fused) {
+    if (mode != HAAR_SHRINK_HARD && mode != HAAR_SHRINK_SOFT)
+        return set_error(HAAR_ERR_ARG, "mode %d is not a haar_shrink_mode", mode);
+    if (levels > 0 && !thresholds) return set_error(HAAR_ERR_NULL, "thresholds is NULL");
+    for (int j = 0; j < levels; ++j)
+        if (!(thresholds[j] >= 0.0f))
+            return set_error(HAAR_ERR_ARG, "threshold of level %d is negative or NaN", j + 1);
+    if (levels > max_fused)
+        return set_error(HAAR_ERR_UNSUPPORTED, "fused shrinkage runs at most %d levels", max_fused);
+    return HAAR_OK;
+}
+
+int haar_shrink_1d(const void* x, void* y, int64_t length, int32_t levels, int64_t batch,
+                   int32_t dtype, int32_t mode, const float* thresholds, void* stream) {
+    if (length < 1) return set_error(HAAR_ERR_SHAPE, "length %lld < 1", (long long)length);
+    bool nothing = false;
+    int rc = check_common(x, y, length, levels, max_levels(length), batch, dtype, &nothing);
+    if (rc != HAAR_OK) return rc;
+    if ((rc = check_shrink(levels, mode, thresholds, kMaxShrinkLevels)) != HAAR_OK || nothing) return rc;
+    if (rc = fault_injected(); rc != HAAR_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (levels == 0) return copy_levels0(x, y, length * batch * elem_bytes(dtype), s);
+    return run_shrink_1d(x, y, length, levels, batch, dtype, mode, thresholds, s);
+}
+
+int haar_shrink_2d(const void* x, void* y, int64_t height, int64_t width, int32_t levels,
+                   int64_t batch, int32_t dtype, int32_t mode, const float* thresholds, void* stream) {
+    if (height < 1 || width < 1)
+        return set_error(HAAR_ERR_SHAPE, "height %lld / width %lld < 1", (long long)height,
+                         (long long)width);
+    if (height > INT64_MAX / width) return set_error(HAAR_ERR_SHAPE, "height * width overflows");
+    bool nothing = false;
+    int rc = check_common(x, y, height * width, levels, haar_max_levels_2d(height, width), batch,
+                          dtype, &nothing);
+    if (rc != HAAR_OK) return rc;
+    if ((rc = check_shrink(levels, mode, thresholds, kMaxShrinkLevels2D)) != HAAR_OK || nothing) return rc;
+    if (rc = fault_injected(); rc != HAAR_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (levels == 0) return copy_levels0(x, y, height * width * batch * elem_bytes(dtype), s);
+    return run_shrink_2d(x, y, height, width, levels, batch, dtype, mode, thresholds, s);
+}
+
 const char* haar_status_string(int status) {
     switch (status) {
         case HAAR_OK: return "HAAR_OK";
@@ -407,6 +451,7 @@ const char* haar_status_string(int status) {
         case HAAR_ERR_HIP: return "HAAR_ERR_HIP";
         case HAAR_ERR_PLAN: return "HAAR_ERR_PLAN";
         case HAAR_ERR_UNSUPPORTED: return "HAAR_ERR_UNSUPPORTED";
+        case HAAR_ERR_ARG: return "HAAR_ERR_ARG";
         default: return "HAAR_ERR_UNKNOWN";
     }
 }

@@ -115,6 +115,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 }
 
 struct StF32 {
+    static constexpr bool kStream = true;   // outputs go to HBM with streaming stores
     using raw = float;
     static constexpr int kBytes = 4;
     __device__ __forceinline__ static float ld(raw v) { return v; }
@@ -122,13 +123,25 @@ struct StF32 {
 };
 
 struct StBF16 {
+    static constexpr bool kStream = true;   // outputs go to HBM with streaming stores
     using raw = uint16_t;
     static constexpr int kBytes = 2;
     __device__ __forceinline__ static float ld(raw v) { return __uint_as_float((uint32_t)v << 16); }
     __device__ __forceinline__ static raw st(float f) { return f32_to_bf16_rne(f); }
 };
 
+// FP32 coefficients of one tile or chunk held on chip (a packed buffer in
+// LDS, addressed through generic pointers): ordinary stores.
+struct StLds {
+    static constexpr bool kStream = false;
+    using raw = float;
+    static constexpr int kBytes = 4;
+    __device__ __forceinline__ static float ld(raw v) { return v; }
+    __device__ __forceinline__ static raw st(float f) { return f; }
+};
+
 struct StF16 {
+    static constexpr bool kStream = true;   // outputs go to HBM with streaming stores
     using raw = uint16_t;
     static constexpr int kBytes = 2;
     __device__ __forceinline__ static float ld(raw v) {
@@ -210,6 +223,14 @@ __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
     }
 }
 
+template <class S, class T>
+__device__ __forceinline__ void st_s(T v, T* p) {
+    if constexpr (S::kStream)
+        st_any(v, p);
+    else
+        *p = v;
+}
+
 template <class S, int N>
 __device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {
     constexpr int B = N * S::kBytes;
@@ -217,16 +238,16 @@ __device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {
     if constexpr (S::kBytes == 4) {
         if constexpr (N == 4) {
             v4f o = {v[0], v[1], v[2], v[3]};
-            st_any(o, reinterpret_cast<v4f*>(p));
+            st_s<S>(o, reinterpret_cast<v4f*>(p));
         } else if constexpr (N == 2) {
             v2f o = {v[0], v[1]};
-            st_any(o, reinterpret_cast<v2f*>(p));
+            st_s<S>(o, reinterpret_cast<v2f*>(p));
         } else {
-            st_any(v[0], reinterpret_cast<float*>(p));
+            st_s<S>(v[0], reinterpret_cast<float*>(p));
         }
     } else {
         if constexpr (B == 2) {
-            st_any(S::st(v[0]), p);
+            st_s<S>(S::st(v[0]), p);
         } else {
             uint32_t w[B / 4];
 #pragma unroll
@@ -234,19 +255,19 @@ __device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {
                 w[i] = (uint32_t)S::st(v[2 * i]) | ((uint32_t)S::st(v[2 * i + 1]) << 16);
             if constexpr (B == 16) {
                 v4u o = {w[0], w[1], w[2], w[3]};
-                st_any(o, reinterpret_cast<v4u*>(p));
+                st_s<S>(o, reinterpret_cast<v4u*>(p));
             } else if constexpr (B == 8) {
                 v2u o = {w[0], w[1]};
-                st_any(o, reinterpret_cast<v2u*>(p));
+                st_s<S>(o, reinterpret_cast<v2u*>(p));
             } else {
-                st_any((u32e)w[0], reinterpret_cast<u32e*>(p));
+                st_s<S>((u32e)w[0], reinterpret_cast<u32e*>(p));
             }
         }
     }
 }
 
 template <class S>
-__device__ __forceinline__ void st1(typename S::raw* p, float v) { st_any(S::st(v), p); }
+__device__ __forceinline__ void st1(typename S::raw* p, float v) { st_s<S>(S::st(v), p); }
 
 // Ordinary (write-back) store of one element.  Used for the short row pieces
 // of the deepest 2D levels: these cover only part of a cache line each, and

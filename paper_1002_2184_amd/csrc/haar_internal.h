@@ -31,4 +31,15 @@ int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch
 int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype, bool inverse,
            hipStream_t s, int cfg_override);
 
+// Fused shrinkage (analysis, thresholding of the details, synthesis): one
+// chunk of kShrinkChunk samples (1D, levels <= 12) or one 32-row tile (2D,
+// levels <= 5) per work-group.
+constexpr int kMaxShrinkLevels = 12;
+constexpr int kShrinkChunk = 4096, kShrinkChunkThreads = 256;
+constexpr int kMaxShrinkLevels2D = 5;
+int run_shrink_1d(const void* in, void* out, int64_t n, int L, int64_t batch, int dtype, int mode,
+                  const float* thr, hipStream_t s);
+int run_shrink_2d(const void* in, void* out, int64_t h, int64_t w, int L, int64_t batch, int dtype,
+                  int mode, const float* thr, hipStream_t s);
+
 }  // namespace haar

@@ -1,0 +1,379 @@
+// Fused shrinkage pipelines: analysis, thresholding of the detail
+// coefficients, synthesis, in one pass over HBM.
+//
+// The applications the paper names (Sec. I, Sec. VI: compression and
+// analysis of biosignals and medical images) decompose a signal, act on its
+// coefficients and reconstruct it.  Run as three calls, that pipeline moves
+// every element through HBM three times; here each work-group does all of it
+// for one chunk (1D) or tile (2D) on chip:
+//   1. the analysis device code of the plain kernels writes the chunk's or
+//      tile's coefficients into a packed buffer in LDS (a chunk or tile whose
+//      origin is a multiple of 2^L is its own subtree of the transform, and a
+//      ragged last chunk or tile follows the same carry rule as the whole
+//      signal, so its coefficients are those of the full transform);
+//   2. every detail coefficient of level j is thresholded with thr[j-1]
+//      (hard: kept when |d| > t, else 0; soft: sign(d) max(|d| - t, 0)); the
+//      approximation a_L / LL_L is kept;
+//   3. the synthesis device code reads the buffer and writes the output.
+// HBM traffic: the input once, the output once.
+//
+// Full 2D tiles take a register path instead: the synthesis of a thread's
+// register block needs exactly the level-1/2 details that the analysis of
+// the same block produced, so those stay in registers (thresholded in
+// place), and only the tile's LL2 region crosses LDS, where one wavefront
+// runs levels 3..L of the analysis, the thresholding and the synthesis.
+#include "haar_1d_chunk.h"
+#include "haar_2d_tile.h"
+#include "haar_internal.h"
+
+namespace haar {
+
+struct ShrinkArgs {
+    float thr[kMaxShrinkLevels];
+    int mode;
+};
+
+__device__ __forceinline__ float shrink_value(float d, int mode, float t) {
+    if (mode == 0) return fabsf(d) > t ? d : 0.0f;
+    const float m = fabsf(d) - t;
+    return m > 0.0f ? copysignf(m, d) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// 1D: chunks of NT * E samples (levels <= log2 of the chunk)
+// ---------------------------------------------------------------------------
+// FULL: the complete chunks of every item (chunks_per_item = n / C of them);
+// otherwise the ragged last chunk of every item (chunks_per_item = 1).
+template <class S, int E, int NT, bool FULL>
+__global__ __launch_bounds__(NT) void shrink1d_kernel(const void* x, void* y, int64_t n, int L,
+                                                      int64_t chunks_per_item, int64_t total,
+                                                      ShrinkArgs sh) {
+    using G = Geo1D<S, E, NT>;
+    constexpr int C = G::C, NW = G::NW;
+    __shared__ float buf[C];                 // the chunk's packed coefficients
+    __shared__ df smd[NW];
+    __shared__ float smf[NW * 8];
+    __shared__ float thr[kMaxShrinkLevels];
+    if (threadIdx.x < kMaxShrinkLevels) thr[threadIdx.x] = sh.thr[threadIdx.x];
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t item = b / chunks_per_item;
+        const int64_t chunk = FULL ? b - item * chunks_per_item : n / C;
+        const int64_t c0 = chunk * C;
+        const int cl = FULL ? C : (int)(n - c0);
+        Pass1D p{};
+        p.n = cl;
+        p.batch = 1;
+        p.levels = L;
+        p.vec_ok = 1;
+        p.src = reinterpret_cast<const typename S::raw*>(x) + item * n + c0;
+        p.det = buf;
+        p.ll = buf;
+        fwd1d_chunk<S, StLds, StLds, E, NT, FULL>(p, 0, 0, smd);
+        __syncthreads();
+        // details of level j occupy [ceil(cl / 2^j), ceil(cl / 2^(j-1)))
+        for (int i = (int)ceil_shift(cl, L) + (int)threadIdx.x; i < cl; i += NT) {
+            int j = 1;
+            while (i < ceil_shift(cl, j)) ++j;
+            buf[i] = shrink_value(buf[i], sh.mode, thr[j - 1]);
+        }
+        __syncthreads();
+        p.dst = reinterpret_cast<typename S::raw*>(y) + item * n + c0;
+        inv1d_chunk<S, StLds, StLds, E, NT, FULL>(p, 0, 0, smf);
+        __syncthreads();                     // LDS reuse by the next chunk
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D: tiles of 32 rows x GX 16-byte vectors (levels <= 5)
+// ---------------------------------------------------------------------------
+// Partial tiles (right column, bottom row), LDS-buffer path: edge tile e of
+// an item is (ty = e, tx = full_x) for e < right, else (ty = full_y,
+// tx = e - right).
+template <class S, int GY, int GX>
+__global__ __launch_bounds__(GY* GX) void shrink2d_edge_kernel(const void* x, void* y, int64_t h, int64_t w,
+                                                               int L, int64_t full_x, int64_t full_y,
+                                                               int64_t right, int64_t bottom,
+                                                               int64_t total, ShrinkArgs sh) {
+    constexpr int RX = 16 / S::kBytes;
+    using G = Geo2D<S, 4, RX, GY, GX>;
+    using In = InvInT<S, StLds, StLds, 4, RX, GY, GX>;
+    constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
+    constexpr int SMF = G::SMEM, SMI = G::AN + G::BN + G::QPT * G::NT;
+    __shared__ float buf[TH * TW];           // the tile's packed coefficients (pitch TW)
+    __shared__ float sm[SMF > SMI ? SMF : SMI];
+    __shared__ float thr[kMaxShrinkLevels];
+    if (threadIdx.x < kMaxShrinkLevels) thr[threadIdx.x] = sh.thr[threadIdx.x];
+    const int64_t per = right + bottom;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t item = b / per, e = b - item * per;
+        const int64_t ty = e < right ? e : full_y, tx = e < right ? full_x : e - right;
+        const int64_t r0 = ty * TH, c0 = tx * TW;
+        const int th = h - r0 < TH ? (int)(h - r0) : TH;
+        const int tw = w - c0 < TW ? (int)(w - c0) : TW;
+        const int64_t origin = item * h * w + r0 * w + c0;
+
+        Pass2D p{};
+        p.h = th;
+        p.w = tw;
+        p.batch = 1;
+        p.levels = L;
+        p.vec_ok = 1;
+        p.src = reinterpret_cast<const typename S::raw*>(x) + origin;
+        p.src_pitch = w;
+        p.det = buf;
+        p.ll = buf;
+        p.det_pitch = p.ll_pitch = TW;
+        {
+            FwdIn<4, RX> in;
+            fwd2d_load<S, 4, RX, GY, GX, false>(p, 0, 0, 0, in);
+            fwd2d_body<S, StLds, StLds, 4, RX, GY, GX, false>(p, 0, 0, 0, in, sm);
+        }
+        __syncthreads();
+        // level j bands: inside the level-(j-1) LL region, outside level j's
+        for (int e = threadIdx.x; e < th * tw; e += NT) {
+            const int rr = e / tw, cc = e - rr * tw;
+            int j = 1;
+            while (j <= L && rr < ceil_shift(th, j) && cc < ceil_shift(tw, j)) ++j;
+            if (j <= L) buf[rr * TW + cc] = shrink_value(buf[rr * TW + cc], sh.mode, thr[j - 1]);
+        }
+        __syncthreads();
+        p.dst = reinterpret_cast<typename S::raw*>(y) + origin;
+        p.dst_pitch = w;
+        {
+            In in;
+            inv2d_load<S, StLds, StLds, 4, RX, GY, GX, false>(p, 0, 0, 0, in);
+            inv2d_body<S, StLds, StLds, 4, RX, GY, GX, false>(p, 0, 0, 0, in, sm);
+        }
+        __syncthreads();                     // LDS reuse by the next tile
+    }
+}
+
+// Full tiles, register path.  LL2 region of the tile: RH x RW = (TH/4) x (TW/4).
+template <class S, int GY, int GX>
+__global__ __launch_bounds__(GY* GX) void shrink2d_full_kernel(const void* x, void* y, int64_t h,
+                                                               int64_t w, int L, int64_t full_x,
+                                                               int64_t full_y, int64_t total,
+                                                               ShrinkArgs sh) {
+    constexpr int RX = 16 / S::kBytes, RY = 4;
+    constexpr int TH = RY * GY, TW = RX * GX;
+    constexpr int B1Y = RY / 2, B1X = RX / 2, B2X = RX / 4;
+    constexpr int RH = TH / 4, RW = TW / 4;
+    // LDS: LL ping-pong (RH x RW each) and the details of levels 3..5
+    constexpr int DET = 3 * ((RH / 2) * (RW / 2) + (RH / 4) * (RW / 4) + (RH / 8) * (RW / 8));
+    __shared__ float lla[RH * RW], llb[RH * RW], dets[DET];
+    __shared__ float thr[kMaxShrinkLevels];
+    const int t = threadIdx.x, rg = t / GX, cg = t % GX;
+    const int lr0 = rg * RY, lc0 = cg * RX;
+    if (t < kMaxShrinkLevels) thr[t] = sh.thr[t];
+    const int mode = sh.mode;
+    const float t1 = sh.thr[0], t2 = sh.thr[1];
+    const int64_t per = full_x * full_y;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t item = b / per, r = b - item * per;
+        const int64_t ty = r / full_x, tx = r - ty * full_x;
+        const int64_t origin = item * h * w + ty * TH * w + tx * TW;
+        const typename S::raw* src = reinterpret_cast<const typename S::raw*>(x) + origin;
+        typename S::raw* dst = reinterpret_cast<typename S::raw*>(y) + origin;
+
+        float v[RY][RX];
+#pragma unroll
+        for (int i = 0; i < RY; ++i) ld_vec<S, RX>(src + (int64_t)(lr0 + i) * w + lc0, v[i]);
+
+        // ---- analysis, levels 1 and 2 (details thresholded in registers)
+        df a1[B1Y][B1X];
+        float hl1[B1Y][B1X], lh1[B1Y][B1X], hh1[B1Y][B1X];
+#pragma unroll
+        for (int i = 0; i < B1Y; ++i)
+#pragma unroll
+            for (int k = 0; k < B1X; ++k) {
+                ana_full_f(v[2 * i][2 * k], v[2 * i][2 * k + 1], v[2 * i + 1][2 * k], v[2 * i + 1][2 * k + 1],
+                           a1[i][k], hl1[i][k], lh1[i][k], hh1[i][k]);
+                hl1[i][k] = shrink_value(hl1[i][k], mode, t1);
+                lh1[i][k] = shrink_value(lh1[i][k], mode, t1);
+                hh1[i][k] = shrink_value(hh1[i][k], mode, t1);
+            }
+        float ll1[B1Y][B1X];
+        if (L == 1) {
+#pragma unroll
+            for (int i = 0; i < B1Y; ++i)
+#pragma unroll
+                for (int k = 0; k < B1X; ++k) ll1[i][k] = df_round(a1[i][k]);
+        } else {
+            df a2[B2X];
+            float hl2[B2X], lh2[B2X], hh2[B2X], ll2[B2X];
+#pragma unroll
+            for (int k = 0; k < B2X; ++k) {
+                ana_full_df(a1[0][2 * k], a1[0][2 * k + 1], a1[1][2 * k], a1[1][2 * k + 1], a2[k], hl2[k],
+                            lh2[k], hh2[k]);
+                hl2[k] = shrink_value(hl2[k], mode, t2);
+                lh2[k] = shrink_value(lh2[k], mode, t2);
+                hh2[k] = shrink_value(hh2[k], mode, t2);
+                ll2[k] = df_round(a2[k]);
+            }
+            if (L >= 3) {
+                // ---- levels 3..L on the LL2 region, by the first wavefront
+#pragma unroll
+                for (int k = 0; k < B2X; ++k) lla[(lr0 >> 2) * RW + (lc0 >> 2) + k] = ll2[k];
+                __syncthreads();
+                if (t < 64) {
+                    float* cur = lla;
+                    float* nxt = llb;
+                    int doff[6];
+                    int off = 0, ch = RH, cw = RW;
+                    for (int lev = 3; lev <= L; ++lev) {          // analysis + threshold
+                        const int bh = ch >> 1, bw = cw >> 1, nb = bh * bw;
+                        doff[lev] = off;
+                        const float tl = thr[lev - 1];
+                        for (int q = t; q < nb; q += 64) {
+                            const int i = q / bw, k = q - i * bw;
+                            const float x00 = cur[(2 * i) * cw + 2 * k], x01 = cur[(2 * i) * cw + 2 * k + 1];
+                            const float x10 = cur[(2 * i + 1) * cw + 2 * k], x11 = cur[(2 * i + 1) * cw + 2 * k + 1];
+                            df ll;
+                            float hl, lh, hh;
+                            ana_full_f(x00, x01, x10, x11, ll, hl, lh, hh);
+                            nxt[q] = df_round(ll);
+                            dets[off + q] = shrink_value(hl, mode, tl);
+                            dets[off + nb + q] = shrink_value(lh, mode, tl);
+                            dets[off + 2 * nb + q] = shrink_value(hh, mode, tl);
+                        }
+                        off += 3 * nb;
+                        ch = bh;
+                        cw = bw;
+                        float* tmp = cur;
+                        cur = nxt;
+                        nxt = tmp;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                    for (int lev = L; lev >= 3; --lev) {          // synthesis
+                        const int bh = ch, bw = cw, nb = bh * bw, ow = 2 * bw;
+                        const int o = doff[lev];
+                        for (int q = t; q < nb; q += 64) {
+                            const int i = q / bw, k = q - i * bw;
+                            float x00, x01, x10, x11;
+                            syn_edge(cur[q], dets[o + q], dets[o + nb + q], dets[o + 2 * nb + q], true, true,
+                                     x00, x01, x10, x11);
+                            nxt[(2 * i) * ow + 2 * k] = x00;
+                            nxt[(2 * i) * ow + 2 * k + 1] = x01;
+                            nxt[(2 * i + 1) * ow + 2 * k] = x10;
+                            nxt[(2 * i + 1) * ow + 2 * k + 1] = x11;
+                        }
+                        ch = 2 * bh;
+                        cw = 2 * bw;
+                        float* tmp = cur;
+                        cur = nxt;
+                        nxt = tmp;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                    // analysis and synthesis swapped the buffers L - 2 times
+                    // each: the reconstructed LL2 region (pitch RW) is in lla
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < B2X; ++k) ll2[k] = lla[(lr0 >> 2) * RW + (lc0 >> 2) + k];
+            }
+            // ---- synthesis, level 2
+#pragma unroll
+            for (int k = 0; k < B2X; ++k)
+                syn_edge(ll2[k], hl2[k], lh2[k], hh2[k], true, true, ll1[0][2 * k], ll1[0][2 * k + 1],
+                         ll1[1][2 * k], ll1[1][2 * k + 1]);
+        }
+        // ---- synthesis, level 1, and the output block
+#pragma unroll
+        for (int i = 0; i < B1Y; ++i)
+#pragma unroll
+            for (int k = 0; k < B1X; ++k)
+                syn_edge(ll1[i][k], hl1[i][k], lh1[i][k], hh1[i][k], true, true, v[2 * i][2 * k],
+                         v[2 * i][2 * k + 1], v[2 * i + 1][2 * k], v[2 * i + 1][2 * k + 1]);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) st_vec<S, RX>(dst + (int64_t)(lr0 + i) * w + lc0, v[i]);
+        if (L >= 3) __syncthreads();         // LDS reuse by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static ShrinkArgs shrink_args(int L, int mode, const float* thr) {
+    ShrinkArgs a{};
+    for (int j = 0; j < L && j < kMaxShrinkLevels; ++j) a.thr[j] = thr[j];
+    a.mode = mode;
+    return a;
+}
+
+constexpr int64_t kMaxGridShrink = 1 << 20;
+
+template <class S>
+static hipError_t launch_shrink1d(const void* x, void* y, int64_t n, int L, int64_t batch,
+                                  const ShrinkArgs& a, hipStream_t s) {
+    constexpr int NT = kShrinkChunkThreads, E = kShrinkChunk / kShrinkChunkThreads;
+    const int64_t per = n / kShrinkChunk, total = per * batch;
+    if (total > 0) {
+        const unsigned grid = (unsigned)(total < kMaxGridShrink ? total : kMaxGridShrink);
+        hipLaunchKernelGGL((shrink1d_kernel<S, E, NT, true>), dim3(grid), dim3(NT), 0, s, x, y, n, L, per,
+                           total, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n % kShrinkChunk != 0) {
+        const unsigned grid = (unsigned)(batch < kMaxGridShrink ? batch : kMaxGridShrink);
+        hipLaunchKernelGGL((shrink1d_kernel<S, E, NT, false>), dim3(grid), dim3(NT), 0, s, x, y, n, L,
+                           (int64_t)1, batch, a);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <class S>
+static hipError_t launch_shrink2d(const void* x, void* y, int64_t h, int64_t w, int L, int64_t batch,
+                                  const ShrinkArgs& a, hipStream_t s) {
+    constexpr int GY = 8, GX = 32, TH = 4 * GY, TW = GX * (16 / S::kBytes);
+    const int64_t tiles_x = (w + TW - 1) / TW, tiles_y = (h + TH - 1) / TH;
+    const int64_t full_x = w / TW, full_y = h / TH;
+    const int64_t interior = full_x * full_y * batch;
+    if (interior > 0) {
+        const unsigned grid = (unsigned)(interior < kMaxGridShrink ? interior : kMaxGridShrink);
+        hipLaunchKernelGGL((shrink2d_full_kernel<S, GY, GX>), dim3(grid), dim3(GY * GX), 0, s, x, y, h, w,
+                           L, full_x, full_y, interior, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int64_t right = tiles_x > full_x ? full_y : 0, bottom = tiles_y > full_y ? tiles_x : 0;
+    const int64_t edge = (right + bottom) * batch;
+    if (edge > 0) {
+        const unsigned grid = (unsigned)(edge < kMaxGridShrink ? edge : kMaxGridShrink);
+        hipLaunchKernelGGL((shrink2d_edge_kernel<S, GY, GX>), dim3(grid), dim3(GY * GX), 0, s, x, y, h, w,
+                           L, full_x, full_y, right, bottom, edge, a);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+int run_shrink_1d(const void* in, void* out, int64_t n, int L, int64_t batch, int dtype, int mode,
+                  const float* thr, hipStream_t s) {
+    const ShrinkArgs a = shrink_args(L, mode, thr);
+    hipError_t e;
+    switch (dtype) {
+        case 0: e = launch_shrink1d<StF32>(in, out, n, L, batch, a, s); break;
+        case 1: e = launch_shrink1d<StBF16>(in, out, n, L, batch, a, s); break;
+        default: e = launch_shrink1d<StF16>(in, out, n, L, batch, a, s); break;
+    }
+    return e == hipSuccess ? 0 : hip_error(e, "shrink1d launch");
+}
+
+int run_shrink_2d(const void* in, void* out, int64_t h, int64_t w, int L, int64_t batch, int dtype,
+                  int mode, const float* thr, hipStream_t s) {
+    const ShrinkArgs a = shrink_args(L, mode, thr);
+    hipError_t e;
+    switch (dtype) {
+        case 0: e = launch_shrink2d<StF32>(in, out, h, w, L, batch, a, s); break;
+        case 1: e = launch_shrink2d<StBF16>(in, out, h, w, L, batch, a, s); break;
+        default: e = launch_shrink2d<StF16>(in, out, h, w, L, batch, a, s); break;
+    }
+    return e == hipSuccess ? 0 : hip_error(e, "shrink2d launch");
+}
+
+}  // namespace haar

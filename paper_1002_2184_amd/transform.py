@@ -96,6 +96,46 @@ def inv2d(y: torch.Tensor, levels: int, out: torch.Tensor | None = None) -> torc
     return x
 
 
+SHRINK_MODES = {"hard": 0, "soft": 1}
+
+
+def _thresholds(levels: int, thresholds):
+    if isinstance(thresholds, (int, float)):
+        return [float(thresholds)] * int(levels)
+    vals = [float(t) for t in thresholds]
+    if len(vals) != int(levels):
+        raise ValueError(f"need one threshold per level ({levels}), got {len(vals)}")
+    return vals
+
+
+def shrink1d(x: torch.Tensor, levels: int, thresholds, mode: str = "hard",
+             out: torch.Tensor | None = None) -> torch.Tensor:
+    """Fused analysis -> thresholding of the level-j details with thresholds[j-1]
+    (one float applies to every level) -> synthesis, along the last axis."""
+    x = _prep(x, 1)
+    y = _out(x, out)
+    n = x.shape[-1]
+    batch = x.numel() // n if n > 0 else 0
+    _abi.check(_abi.haar_shrink_1d(x.data_ptr(), y.data_ptr(), n, int(levels), batch, dtype_code(x),
+                                   SHRINK_MODES[mode], _thresholds(levels, thresholds),
+                                   _stream(x.device)))
+    return y
+
+
+def shrink2d(x: torch.Tensor, levels: int, thresholds, mode: str = "hard",
+             out: torch.Tensor | None = None) -> torch.Tensor:
+    """Fused 2D analysis -> thresholding of the level-j bands with
+    thresholds[j-1] -> synthesis, on the last two axes."""
+    x = _prep(x, 2)
+    y = _out(x, out)
+    h, w = x.shape[-2], x.shape[-1]
+    batch = x.numel() // (h * w) if h * w > 0 else 0
+    _abi.check(_abi.haar_shrink_2d(x.data_ptr(), y.data_ptr(), h, w, int(levels), batch, dtype_code(x),
+                                   SHRINK_MODES[mode], _thresholds(levels, thresholds),
+                                   _stream(x.device)))
+    return y
+
+
 def tune_2d(shape, levels: int, dtype=torch.float32, inverse: bool = False, device="cuda") -> int:
     """Time the 2D tile candidates for [batch, h, w] and record the fastest; returns its index."""
     *lead, h, w = shape

@@ -69,6 +69,15 @@ X, Y = 0x10000000, 0x20000000     # fake, non-overlapping device addresses (neve
     (lambda a: a.haar_inv_2d(X, Y, 8, 8, 1, 1, 3, 0), 2),
     (lambda a: a.haar_inv_2d(X, X, 8, 8, 1, 1, 0, 0), 5),        # in place
     (lambda a: a.haar_fwd_2d(X, Y, 1 << 40, 1 << 40, 1, 1, 0, 0), 3),   # size overflow
+    (lambda a: a.haar_shrink_1d(X, Y, 64, 2, 1, 0, 2, [1.0, 1.0], 0), 10),        # mode
+    (lambda a: a.haar_shrink_1d(X, Y, 64, 2, 1, 0, 0, [1.0, -1.0], 0), 10),       # negative threshold
+    (lambda a: a.haar_shrink_1d(X, Y, 64, 2, 1, 0, 1, [float("nan"), 1.0], 0), 10),
+    (lambda a: a.haar_shrink_1d(X, Y, 64, 2, 1, 0, 0, None, 0), 1),               # no thresholds
+    (lambda a: a.haar_shrink_1d(X, Y, 1 << 14, 13, 1, 0, 0, [1.0] * 13, 0), 9),   # beyond one chunk
+    (lambda a: a.haar_shrink_1d(X, X + 4, 64, 2, 1, 0, 0, [1.0, 1.0], 0), 5),
+    (lambda a: a.haar_shrink_2d(X, Y, 64, 64, 6, 1, 0, 0, [1.0] * 6, 0), 9),      # beyond one tile
+    (lambda a: a.haar_shrink_2d(X, Y, 8, 8, 4, 1, 0, 0, [1.0] * 4, 0), 4),        # levels > log2
+    (lambda a: a.haar_shrink_2d(X, Y, 8, 8, 2, 1, 5, 0, [1.0] * 2, 0), 2),        # dtype
 ])
 def test_validation_codes(abi, call, code):
     assert call(abi) == code
@@ -85,7 +94,14 @@ def test_overlap_detects_tail(abi, monkeypatch):
     assert abi.haar_fwd_2d(X, X + 128, 8, 8, 1, 1, 1, 0) == 7
 
 
+def test_shrink_accepts_infinite_threshold(abi, monkeypatch):
+    monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")     # valid call, stopped before any HIP call
+    assert abi.haar_shrink_2d(X, Y, 64, 64, 2, 1, 0, 1, [float("inf"), 0.0], 0) == 7
+    assert abi.haar_shrink_1d(X, Y, 64, 0, 1, 0, 0, None, 0) == 7        # levels 0: a copy
+
+
 def test_batch_zero_is_a_noop(abi):
+    assert abi.haar_shrink_1d(0, 0, 16, 2, 0, 0, 0, [1.0, 1.0], 0) == 0
     assert abi.haar_fwd_1d(0, 0, 16, 2, 0, 0, 0) == 0
     assert abi.haar_inv_2d(0, 0, 8, 8, 3, 0, 1, 0) == 0
 
@@ -100,6 +116,7 @@ def test_fault_injection_maps_to_hip_error(abi, monkeypatch):
 def test_status_strings(abi):
     assert abi.haar_status_string(0) == "HAAR_OK"
     assert abi.haar_status_string(5) == "HAAR_ERR_ALIAS"
+    assert abi.haar_status_string(10) == "HAAR_ERR_ARG"
     assert abi.haar_status_string(99) == "HAAR_ERR_UNKNOWN"
     assert "gfx950" in abi.haar_version()
 
