@@ -7,42 +7,63 @@ namespace haar {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <class SX, class SD, class SL, int E, int NT>
-__global__ __launch_bounds__(NT) void fwd1d_kernel(Pass1D p) {
+// A launch covers chunks [first, first + per) of every item: the complete
+// chunks (FULL, vector path) and the ragged last chunk of each item (scalar
+// path) run as separate launches, so that neither kernel carries the
+// registers of the other path.
+template <class SX, class SD, class SL, int E, int NT, bool FULL>
+__global__ __launch_bounds__(NT) void fwd1d_kernel(Pass1D p, int64_t first, int64_t per, int64_t total) {
     using G = Geo1D<SX, E, NT>;
     __shared__ df sm[G::NW];
-    const bool remap = p.remap && (int64_t)gridDim.x == p.total_chunks;
-    for (int64_t b = blockIdx.x; b < p.total_chunks; b += gridDim.x) {
-        const int64_t c = remap ? xcd_tile(b, p.total_chunks) : b;
-        const int64_t item = c / p.chunks_per_item, chunk = c - item * p.chunks_per_item;
-        const bool full = p.vec_ok && (chunk + 1) * G::C <= p.n;
-        if (full)
-            fwd1d_chunk<SX, SD, SL, E, NT, true>(p, item, chunk, sm);
-        else
-            fwd1d_chunk<SX, SD, SL, E, NT, false>(p, item, chunk, sm);
-        if (b + gridDim.x < p.total_chunks) __syncthreads();
+    __shared__ float stage[FULL ? NT * E : 1];
+    const bool remap = p.remap && (int64_t)gridDim.x == total;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t c = remap ? xcd_tile(b, total) : b;
+        const int64_t item = c / per, chunk = first + (c - item * per);
+        fwd1d_chunk<SX, SD, SL, E, NT, FULL>(p, item, chunk, sm, stage);
+        if (b + gridDim.x < total) __syncthreads();
     }
 }
 
-template <class SX, class SD, class SL, int E, int NT, bool WALK>
-__global__ __launch_bounds__(NT) void inv1d_kernel(Pass1D p) {
+template <class SX, class SD, class SL, int E, int NT, bool FULL, bool WALK, bool DEEP = false>
+__global__ __launch_bounds__(NT) void inv1d_kernel(Pass1D p, int64_t first, int64_t per, int64_t total) {
     using G = Geo1D<SX, E, NT>;
     __shared__ float sm[G::NW * 8];
-    const bool remap = p.remap && (int64_t)gridDim.x == p.total_chunks;
-    for (int64_t b = blockIdx.x; b < p.total_chunks; b += gridDim.x) {
-        const int64_t c = remap ? xcd_tile(b, p.total_chunks) : b;
-        const int64_t item = c / p.chunks_per_item, chunk = c - item * p.chunks_per_item;
-        const bool full = p.vec_ok && (chunk + 1) * G::C <= p.n;
+    __shared__ float stage[FULL ? NT * E : 1];
+    const bool remap = p.remap && (int64_t)gridDim.x == total;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t c = remap ? xcd_tile(b, total) : b;
+        const int64_t item = c / per, chunk = first + (c - item * per);
         float top = 0.0f;
         if (WALK)
             top = walk_down<SD>(reinterpret_cast<const typename SD::raw*>(p.det) + item * p.det_bstride,
                                 p.n, p.levels_total, p.levels, chunk);
-        if (full)
-            inv1d_chunk<SX, SD, SL, E, NT, true>(p, item, chunk, sm, WALK, top);
-        else
-            inv1d_chunk<SX, SD, SL, E, NT, false>(p, item, chunk, sm, WALK, top);
-        if (b + gridDim.x < p.total_chunks) __syncthreads();
+        inv1d_chunk<SX, SD, SL, E, NT, FULL, DEEP>(p, item, chunk, sm, stage, WALK, top);
+        if (b + gridDim.x < total) __syncthreads();
     }
+}
+
+// Launch the complete chunks (vector path), then the ragged last chunk of
+// every item (or, when the layout forbids vectors, every chunk) on the
+// scalar path.
+template <class KFull, class KPart>
+static hipError_t launch_split1d(const Pass1D& p, int C, int NT, KFull kfull, KPart kpart, hipStream_t s) {
+    constexpr int64_t kMaxGrid = 1 << 20;
+    const int64_t nfull = p.vec_ok ? p.n / C : 0, npart = p.chunks_per_item - nfull;
+    if (nfull > 0) {
+        const int64_t total = nfull * p.batch;
+        const unsigned grid = (unsigned)(total < kMaxGrid ? total : kMaxGrid);
+        hipLaunchKernelGGL(kfull, dim3(grid), dim3(NT), 0, s, p, (int64_t)0, nfull, total);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (npart > 0) {
+        const int64_t total = npart * p.batch;
+        const unsigned grid = (unsigned)(total < kMaxGrid ? total : kMaxGrid);
+        hipLaunchKernelGGL(kpart, dim3(grid), dim3(NT), 0, s, p, nfull, npart, total);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 // Levels lc+1..L of each item's prefix, one work-group per item.
@@ -85,13 +106,15 @@ Chunk1D chunk_config_1d(int index) {
 
 template <class SX, class SD, class SL, int NT, int E>
 static hipError_t launch1d(const Pass1D& p, bool inverse, hipStream_t s) {
-    constexpr int64_t kMaxGrid = 1 << 20;
-    const unsigned grid = (unsigned)(p.total_chunks < kMaxGrid ? p.total_chunks : kMaxGrid);
-    if (inverse)
-        hipLaunchKernelGGL((inv1d_kernel<SX, SD, SL, E, NT, false>), dim3(grid), dim3(NT), 0, s, p);
-    else
-        hipLaunchKernelGGL((fwd1d_kernel<SX, SD, SL, E, NT>), dim3(grid), dim3(NT), 0, s, p);
-    return hipGetLastError();
+    if (inverse) {
+        if (p.levels > Log2<E>::v)
+            return launch_split1d(p, NT * E, NT, inv1d_kernel<SX, SD, SL, E, NT, true, false, true>,
+                                  inv1d_kernel<SX, SD, SL, E, NT, false, false>, s);
+        return launch_split1d(p, NT * E, NT, inv1d_kernel<SX, SD, SL, E, NT, true, false>,
+                              inv1d_kernel<SX, SD, SL, E, NT, false, false>, s);
+    }
+    return launch_split1d(p, NT * E, NT, fwd1d_kernel<SX, SD, SL, E, NT, true>,
+                          fwd1d_kernel<SX, SD, SL, E, NT, false>, s);
 }
 
 template <class S>
@@ -167,10 +190,9 @@ hipError_t launch_finish1d(const Pass1D& p, int dtype, int lc, int L, bool src32
 
 template <class S, int NT, int E>
 static hipError_t walk_t(const Pass1D& p, hipStream_t s) {
-    constexpr int64_t kMaxGrid = 1 << 20;
-    const unsigned grid = (unsigned)(p.total_chunks < kMaxGrid ? p.total_chunks : kMaxGrid);
-    hipLaunchKernelGGL((inv1d_kernel<S, S, S, E, NT, true>), dim3(grid), dim3(NT), 0, s, p);
-    return hipGetLastError();
+    // the walk covers the whole chunk depth, so full chunks are always deep
+    return launch_split1d(p, NT * E, NT, inv1d_kernel<S, S, S, E, NT, true, true, true>,
+                          inv1d_kernel<S, S, S, E, NT, false, true>, s);
 }
 
 template <class S>

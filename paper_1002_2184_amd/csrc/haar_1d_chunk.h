@@ -53,12 +53,64 @@ __device__ __forceinline__ void ld_span(const typename S::raw* p, float* v) {
     for (int q = 0; q < N / V; ++q) ld_vec<S, V>(p + q * V, v + q * V);
 }
 
+// Full chunks read and write HBM lane-contiguously: instruction q of a
+// wavefront covers one contiguous span (64 lanes x 16 bytes), which the memory
+// system serves far better than a thread-contiguous layout (each thread's E
+// samples as consecutive vectors, so that one instruction touches every
+// cache line of the wavefront's slice only partly).  The compute layout stays
+// thread-contiguous: wavefront w stages its slice of NT/64 ... through LDS
+// (`stage`, 64 * E floats per wavefront, wavefront-local ordering only).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class SX, int E>
+__device__ __forceinline__ void ld_chunk_lanes(const typename SX::raw* src, float* stage, float (&x)[E],
+                                               int lane, int wv) {
+    constexpr int VEC = 16 / SX::kBytes, NV = E / VEC;
+    const typename SX::raw* ws = src + (int64_t)wv * 64 * E;
+    float* st = stage + wv * 64 * E;
+    float v[NV][VEC];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) ld_vec<SX, VEC>(ws + (q * 64 + lane) * VEC, v[q]);
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) st[(q * 64 + lane) * VEC + e] = v[q][e];
+    wave_sync_lds();
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = st[lane * E + e];
+}
+
+template <class SX, int E>
+__device__ __forceinline__ void st_chunk_lanes(typename SX::raw* dst, float* stage, const float (&a)[E],
+                                               int lane, int wv) {
+    constexpr int VEC = 16 / SX::kBytes, NV = E / VEC;
+    typename SX::raw* ws = dst + (int64_t)wv * 64 * E;
+    float* st = stage + wv * 64 * E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) st[lane * E + e] = a[e];
+    wave_sync_lds();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        float v[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = st[(q * 64 + lane) * VEC + e];
+        st_vec<SX, VEC>(ws + (q * 64 + lane) * VEC, v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Analysis: in-thread levels (template recursion keeps register indices static)
 // ---------------------------------------------------------------------------
+// wst: this wavefront's LDS slice (64 * E floats, free once the input has
+// been read from it), used to store spans wider than 16 bytes per thread
+// lane-contiguously.
 template <class SD, int E, bool FULL, int LEV>
 __device__ __forceinline__ void fwd_thread_levels(df (&s)[E], int L, int t, int cl, int64_t n,
-                                                  int64_t c0, typename SD::raw* det) {
+                                                  int64_t c0, typename SD::raw* det, float* wst) {
     constexpr int LOG_E = Log2<E>::v;
     if constexpr (LEV <= LOG_E) {
         if (LEV > L) return;
@@ -78,19 +130,65 @@ __device__ __forceinline__ void fwd_thread_levels(df (&s)[E], int L, int t, int 
                 s[m] = a;
         }
         typename SD::raw* dp = det + ceil_shift(n, LEV) + (c0 >> LEV) + (int64_t)t * CNT;
-        if constexpr (FULL) {
+        if constexpr (FULL && SD::kStream && CNT * SD::kBytes > 16) {
+            constexpr int V = 16 / SD::kBytes;
+            const int lane = t & 63;
+            typename SD::raw* wb = dp - (int64_t)lane * CNT;   // the wavefront's segment
+            wave_sync_lds();                                   // the slice's input reads are done
+#pragma unroll
+            for (int m = 0; m < CNT; ++m) wst[lane * CNT + m] = d[m];
+            wave_sync_lds();
+#pragma unroll
+            for (int q = 0; q < CNT / V; ++q) {
+                float o[V];
+#pragma unroll
+                for (int e = 0; e < V; ++e) o[e] = wst[(q * 64 + lane) * V + e];
+                st_vec<SD, V>(wb + (q * 64 + lane) * V, o);
+            }
+        } else if constexpr (FULL) {
             st_span<SD, CNT>(dp, d);
         } else {
 #pragma unroll
             for (int m = 0; m < CNT; ++m)
                 if (2 * (t * CNT + m) + 1 < len) st1<SD>(dp + m, d[m]);
         }
-        fwd_thread_levels<SD, E, FULL, LEV + 1>(s, L, t, cl, n, c0, det);
+        fwd_thread_levels<SD, E, FULL, LEV + 1>(s, L, t, cl, n, c0, det, wst);
+    }
+}
+
+// The E >> L approximations of a thread after L <= log2(E) in-thread levels,
+// normalised and stored as one span (L is a runtime value: the template
+// recursion selects the span length).
+template <class SL, int E, int LEV>
+__device__ __forceinline__ void st_approx(const df (&s)[E], int L, typename SL::raw* base, int t) {
+    if constexpr ((E >> LEV) >= 1) {
+        if (L == LEV) {
+            constexpr int CNT = E >> LEV;
+            float o[CNT];
+#pragma unroll
+            for (int m = 0; m < CNT; ++m) o[m] = df_norm(s[m], LEV);
+            st_span<SL, CNT>(base + (int64_t)t * CNT, o);
+            return;
+        }
+        st_approx<SL, E, LEV + 1>(s, L, base, t);
+    }
+}
+
+template <class SL, int E, int LEV>
+__device__ __forceinline__ void ld_approx(float (&a)[E], int L, const typename SL::raw* base, int t) {
+    if constexpr ((E >> LEV) >= 1) {
+        if (L == LEV) {
+            constexpr int CNT = E >> LEV;
+            ld_span<SL, CNT>(base + (int64_t)t * CNT, a);
+            return;
+        }
+        ld_approx<SL, E, LEV + 1>(a, L, base, t);
     }
 }
 
 template <class SX, class SD, class SL, int E, int NT, bool FULL>
-__device__ __forceinline__ void fwd1d_chunk(const Pass1D& p, int64_t item, int64_t chunk, df* sm) {
+__device__ __forceinline__ void fwd1d_chunk(const Pass1D& p, int64_t item, int64_t chunk, df* sm,
+                                            float* stage) {
     using G = Geo1D<SX, E, NT>;
     constexpr int C = G::C, LOG_E = G::LOG_E, VEC = G::VEC;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -103,8 +201,7 @@ __device__ __forceinline__ void fwd1d_chunk(const Pass1D& p, int64_t item, int64
 
     float x[E];
     if constexpr (FULL) {
-#pragma unroll
-        for (int q = 0; q < E / VEC; ++q) ld_vec<SX, VEC>(src + t * E + q * VEC, x + q * VEC);
+        ld_chunk_lanes<SX, E>(src, stage, x, lane, wv);
     } else {
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = (t * E + e < cl) ? ld1<SX>(src + t * E + e) : 0.0f;
@@ -112,14 +209,18 @@ __device__ __forceinline__ void fwd1d_chunk(const Pass1D& p, int64_t item, int64
     df s[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) s[e] = df_from(x[e]);
-    fwd_thread_levels<SD, E, FULL, 1>(s, L, t, cl, n, c0, det);
+    fwd_thread_levels<SD, E, FULL, 1>(s, L, t, cl, n, c0, det, FULL ? stage + wv * 64 * E : nullptr);
 
     if (L <= LOG_E) {                    // approximations straight from registers
-        const int cnt = E >> L;          // runtime count (power of two)
-        const int lenL = (int)ceil_shift(cl, L);
+        if constexpr (FULL) {
+            st_approx<SL, E, 1>(s, L, llp + (c0 >> L), t);
+        } else {
+            const int cnt = E >> L;      // runtime count (power of two)
+            const int lenL = (int)ceil_shift(cl, L);
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-            if (m < cnt && t * cnt + m < lenL) st1<SL>(llp + (c0 >> L) + t * cnt + m, df_norm(s[m], L));
+            for (int m = 0; m < E; ++m)
+                if (m < cnt && t * cnt + m < lenL) st1<SL>(llp + (c0 >> L) + t * cnt + m, df_norm(s[m], L));
+        }
         return;
     }
 
@@ -182,9 +283,14 @@ __device__ __forceinline__ void fwd1d_chunk(const Pass1D& p, int64_t item, int64
 // has_top: the chunk's single deepest approximation (the pass covers the
 // whole on-chip depth, so a chunk holds one value at its deepest level) is
 // supplied by the caller in `top` instead of being read from p.ll.
-template <class SX, class SD, class SL, int E, int NT, bool FULL>
+// DEEP (full chunks, L > log2(E)): every in-thread level is present and all
+// loads are issued as straight-line code (a lane that holds no value of a
+// wavefront level reads its group's value: same address, same cache line), so
+// that no branch separates them and they overlap in one memory round trip.
+template <class SX, class SD, class SL, int E, int NT, bool FULL, bool DEEP = false>
 __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64_t chunk, float* sm,
-                                            bool has_top = false, float top = 0.0f) {
+                                            float* stage, bool has_top = false, float top = 0.0f) {
+    static_assert(!DEEP || FULL, "the straight-line loads need a full chunk");
     using G = Geo1D<SX, E, NT>;
     constexpr int C = G::C, LOG_E = G::LOG_E, VEC = G::VEC, NW = G::NW;
     constexpr int VECD = 16 / SD::kBytes;
@@ -201,7 +307,7 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
     float dl[E];
 #pragma unroll
     for (int lev = 1; lev <= LOG_E; ++lev) {
-        if (lev > L) break;
+        if (!DEEP && lev > L) break;
         const int cnt = E >> lev;
         const int len = (int)ceil_shift(cl, lev - 1);
         const typename SD::raw* dp = det + ceil_shift(n, lev) + (c0 >> lev) + (int64_t)t * cnt;
@@ -227,12 +333,35 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
 #pragma unroll
     for (int st = 0; st < 6; ++st) {
         const int lev = LOG_E + 1 + st;
-        dw[st] = 0.0f;
-        if (lev <= L && (lane & ((2 << st) - 1)) == 0) {
-            const int P = t >> (st + 1);
-            if (2 * P + 1 < (int)ceil_shift(cl, lev - 1))
-                dw[st] = ld1<SD>(det + ceil_shift(n, lev) + (c0 >> lev) + P);
+        if constexpr (DEEP) {
+            const int lv = lev <= L ? lev : L;           // a level of the transform (> LOG_E)
+            const int P = t >> (lv - LOG_E);
+            dw[st] = ld1<SD>(det + ceil_shift(n, lv) + (c0 >> lv) + P);
+        } else {
+            dw[st] = 0.0f;
+            if (lev <= L && (lane & ((2 << st) - 1)) == 0) {
+                const int P = t >> (st + 1);
+                if (2 * P + 1 < (int)ceil_shift(cl, lev - 1))
+                    dw[st] = ld1<SD>(det + ceil_shift(n, lev) + (c0 >> lev) + P);
+            }
         }
+    }
+
+    // DEEP: the values of the cross-wavefront levels (details of levels
+    // LOG_E+7..L, then a_L) join the same load phase (clamped indices)
+    constexpr int LOG_NW = G::LOG_NW;
+    float topv[LOG_NW + 1];
+    if constexpr (DEEP) {
+#pragma unroll
+        for (int k = 0; k < LOG_NW; ++k) {
+            const int lev = LOG_E + 7 + k;
+            const int lv = lev <= L ? lev : L;
+            const int nd = (int)ceil_shift(cl, lv - 1) >> 1;
+            const int ti = t < nd ? t : nd - 1;
+            topv[k] = ld1<SD>(det + ceil_shift(n, lv) + (c0 >> lv) + ti);
+        }
+        const int na = (int)ceil_shift(cl, L);
+        topv[LOG_NW] = has_top ? top : ld1<SL>(llp + (c0 >> L) + (t < na ? t : na - 1));
     }
 
     float v = 0.0f;   // a_{min(L, LOG_E+6)} value held by wave-level lanes
@@ -247,11 +376,23 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
             for (int lev = wtop + 1; lev <= L; ++lev) {
                 const int len = (int)ceil_shift(cl, lev - 1);
                 const int nd = len >> 1;
-                if (t < nd) sd[off + t] = ld1<SD>(det + ceil_shift(n, lev) + (c0 >> lev) + t);
+                if constexpr (DEEP) {
+                    float tvk = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < LOG_NW; ++k)
+                        if (lev == wtop + 1 + k) tvk = topv[k];
+                    if (t < nd) sd[off + t] = tvk;
+                } else {
+                    if (t < nd) sd[off + t] = ld1<SD>(det + ceil_shift(n, lev) + (c0 >> lev) + t);
+                }
                 off += NW;
             }
             const int na = (int)ceil_shift(cl, L);
-            if (t < na) sa[t] = has_top ? top : ld1<SL>(llp + (c0 >> L) + t);
+            if constexpr (DEEP) {
+                if (t < na) sa[t] = topv[LOG_NW];
+            } else {
+                if (t < na) sa[t] = has_top ? top : ld1<SL>(llp + (c0 >> L) + t);
+            }
         }
         __syncthreads();
         if (t == 0) {
@@ -272,6 +413,8 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
         }
         __syncthreads();
         if (lane == 0 && wv < (int)ceil_shift(cl, wtop)) v = sa[wv];
+    } else if (DEEP) {
+        v = has_top ? top : ld1<SL>(llp + (c0 >> L) + (t >> (L - LOG_E)));
     } else if (L > LOG_E) {
         const int st = L - LOG_E;
         const int P = t >> st;
@@ -304,6 +447,8 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
     float a[E];
     if (L > LOG_E) {
         a[0] = v;
+    } else if constexpr (FULL) {
+        ld_approx<SL, E, 1>(a, L, llp + (c0 >> L), t);
     } else {
         const int cnt = E >> L;
         const int lenL = (int)ceil_shift(cl, L);
@@ -332,8 +477,7 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
         }
     }
     if constexpr (FULL) {
-#pragma unroll
-        for (int q = 0; q < E / VEC; ++q) st_vec<SX, VEC>(dst + t * E + q * VEC, a + q * VEC);
+        st_chunk_lanes<SX, E>(dst, stage, a, lane, wv);
     } else {
 #pragma unroll
         for (int e = 0; e < E; ++e)

@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
     constexpr int NW = kPlanNT1 / 64;
     __shared__ df smd[NW];
     __shared__ float smf[NW * 8];
+    __shared__ float stage[kPlanC1];
     __shared__ unsigned s_slot;
     walk_units<DYN>(nunits, ctr, &s_slot, [&](unsigned unit) {
         const PlanChunk1D d = chunks[unit];
@@ -185,15 +186,15 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
             if (it.levels > it.chunk_levels) {
                 p.ll = a32 + it.a32;
                 if (full)
-                    fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd);
+                    fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd, stage);
                 else
-                    fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd);
+                    fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd, stage);
             } else {
                 p.ll = it.out;
                 if (full)
-                    fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd);
+                    fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd, stage);
                 else
-                    fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd);
+                    fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd, stage);
             }
         } else {
             p.det = const_cast<void*>(it.in);
@@ -204,9 +205,9 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
                                                   it.levels, kPlanLogC1, d.chunk)
                                    : 0.0f;
             if (full)
-                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smf, deep, top);
+                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smf, stage, deep, top);
             else
-                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smf, deep, top);
+                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smf, stage, deep, top);
         }
     });
 }

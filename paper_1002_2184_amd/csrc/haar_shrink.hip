@@ -51,6 +51,7 @@ __global__ __launch_bounds__(NT) void shrink1d_kernel(const void* x, void* y, in
     using G = Geo1D<S, E, NT>;
     constexpr int C = G::C, NW = G::NW;
     __shared__ float buf[C];                 // the chunk's packed coefficients
+    __shared__ float stage[FULL ? C : 1];    // lane-contiguous HBM access of full chunks
     __shared__ df smd[NW];
     __shared__ float smf[NW * 8];
     __shared__ float thr[kMaxShrinkLevels];
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(NT) void shrink1d_kernel(const void* x, void* y, in
         p.src = reinterpret_cast<const typename S::raw*>(x) + item * n + c0;
         p.det = buf;
         p.ll = buf;
-        fwd1d_chunk<S, StLds, StLds, E, NT, FULL>(p, 0, 0, smd);
+        fwd1d_chunk<S, StLds, StLds, E, NT, FULL>(p, 0, 0, smd, stage);
         __syncthreads();
         // details of level j occupy [ceil(cl / 2^j), ceil(cl / 2^(j-1)))
         for (int i = (int)ceil_shift(cl, L) + (int)threadIdx.x; i < cl; i += NT) {
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(NT) void shrink1d_kernel(const void* x, void* y, in
         }
         __syncthreads();
         p.dst = reinterpret_cast<typename S::raw*>(y) + item * n + c0;
-        inv1d_chunk<S, StLds, StLds, E, NT, FULL>(p, 0, 0, smf);
+        inv1d_chunk<S, StLds, StLds, E, NT, FULL>(p, 0, 0, smf, stage);
         __syncthreads();                     // LDS reuse by the next chunk
     }
 }
