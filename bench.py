@@ -343,6 +343,37 @@ def suite():
                       "us_plain_fwd_inv": round(ms_p1 * 1e3, 2),
                       "speedup_vs_fwd_inv": round(ms_p1 / ms_f1, 2)}), flush=True)
 
+    # 7) the direct (convolve-then-decimate) bank of Fig. 1 / Fig. 5 beside
+    #    the fast bank, same signals (256 x 65536, 12 levels)
+    from paper_1002_2184_amd import _abi
+    ws = torch.empty(_abi.haar_direct_workspace_size(x1.shape[1], x1.shape[0]), dtype=torch.uint8, device=dev)
+    kk[0] = 0
+
+    def dfwd():
+        k = kk[0] = (kk[0] + 1) % 4
+        T.direct1d(x1s[k], 12, out=y1s[k], workspace=ws)
+
+    def dinv():
+        k = kk[0] = (kk[0] + 1) % 4
+        T.direct1d(y1s[k], 12, inverse=True, out=x1s[(k + 2) % 4], workspace=ws)
+
+    def ffwd():
+        k = kk[0] = (kk[0] + 1) % 4
+        T.fwd1d(x1s[k], 12, out=y1s[k])
+
+    def finv():
+        k = kk[0] = (kk[0] + 1) % 4
+        T.inv1d(y1s[k], 12, out=x1s[(k + 2) % 4])
+    res = {"workload": "1d-256x65536-L12 direct vs fast bank"}
+    for name, fn in (("direct_fwd", dfwd), ("direct_inv", dinv), ("fast_fwd", ffwd), ("fast_inv", finv)):
+        ms = _timed(fn, 16, 4, st)
+        res[f"us_{name}"] = round(ms * 1e3, 2)
+        res[f"gbps_{name}"] = round(nb1 / (ms * 1e-3) / 1e9, 1)
+    res["fast_speedup_fwd"] = round(res["us_direct_fwd"] / res["us_fast_fwd"], 2)
+    res["fast_speedup_inv"] = round(res["us_direct_inv"] / res["us_fast_inv"], 2)
+    res["note"] = "GB/s = algorithmic bytes (read + write once) / time"
+    print(json.dumps(res), flush=True)
+
 
 def cpu_baseline(x_np, budget_s: float):
     """The FP64 oracle (fwd + inv of the same image) on this host's cores."""

@@ -155,6 +155,27 @@ int haar_shrink_2d(const void* x, void* y, int64_t height, int64_t width,
                    int32_t levels, int64_t batch, int32_t dtype, int32_t mode,
                    const float* thresholds, void* stream);
 
+/* ------------------------------------------------------------------------
+ * The direct ("original") filter bank, for comparison with the fast bank.
+ * Analysis per level (Fig. 1 / Fig. 2, taps of Eq. (8)-(9)): convolve the
+ * approximation with b0 = [1, 1]/sqrt2 and b1 = [1, -1]/sqrt2 at the full
+ * rate, then decimate (keep the odd phase, pairs aligned at even indices).
+ * Synthesis per level (Fig. 5, Eq. (13), taps of Eq. (17)-(18)): up-sample
+ * both channels by zero insertion, filter with a0 = [1, 1]/sqrt2 and
+ * a1 = [-1, 1]/sqrt2, add.  Odd counts carry as in the fast bank, so the
+ * results equal haar_fwd_1d / haar_inv_1d (up to FP32 rounding).
+ * Every stage is a pass over the workspace, which holds the full-rate
+ * streams: the work the fast bank avoids by computing only the decimated
+ * outputs.  Plain FP32 arithmetic; x, y device pointers as in the plain
+ * calls; inverse = 0 analysis, 1 synthesis.  workspace: caller-owned device
+ * memory of at least haar_direct_workspace_size(length, batch) bytes,
+ * 4-byte aligned (HAAR_ERR_WORKSPACE otherwise).
+ * ------------------------------------------------------------------------ */
+size_t haar_direct_workspace_size(int64_t length, int64_t batch);
+int haar_direct_1d(const void* x, void* y, int64_t length, int32_t levels,
+                   int64_t batch, int32_t dtype, int32_t inverse,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
 /* ceil(log2(length)) for length >= 1 (0 for length 1); -1 if length < 1.
  * Beyond this depth every further level would be a no-op. */
 int haar_max_levels_1d(int64_t length);

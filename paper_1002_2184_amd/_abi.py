@@ -48,6 +48,8 @@ _SIGS = {
     "haar_inv_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_shrink_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _I32, _FP, _VP], ctypes.c_int),
     "haar_shrink_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _I32, _FP, _VP], ctypes.c_int),
+    "haar_direct_workspace_size": ([_I64, _I64], ctypes.c_size_t),
+    "haar_direct_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _I32, _VP, _SZ, _VP], ctypes.c_int),
     "haar_max_levels_1d": ([_I64], ctypes.c_int),
     "haar_max_levels_2d": ([_I64, _I64], ctypes.c_int),
     "haar_plan_create_1d": ([ctypes.POINTER(Item1D), _I64, _I32, _I32, ctypes.POINTER(_VP)], ctypes.c_int),
@@ -121,6 +123,15 @@ def haar_shrink_1d(x, y, length, levels, batch, dtype, mode, thresholds, stream=
 
 def haar_shrink_2d(x, y, height, width, levels, batch, dtype, mode, thresholds, stream=0):
     return lib().haar_shrink_2d(x, y, height, width, levels, batch, dtype, mode, _floats(thresholds),
+                                stream)
+
+
+def haar_direct_workspace_size(length, batch):
+    return lib().haar_direct_workspace_size(length, batch)
+
+
+def haar_direct_1d(x, y, length, levels, batch, dtype, inverse, workspace, workspace_bytes, stream=0):
+    return lib().haar_direct_1d(x, y, length, levels, batch, dtype, inverse, workspace, workspace_bytes,
                                 stream)
 
 

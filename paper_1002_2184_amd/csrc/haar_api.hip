@@ -439,6 +439,27 @@ int haar_shrink_2d(const void* x, void* y, int64_t height, int64_t width, int32_
     return run_shrink_2d(x, y, height, width, levels, batch, dtype, mode, thresholds, s);
 }
 
+size_t haar_direct_workspace_size(int64_t length, int64_t batch) {
+    if (length < 1 || batch < 0) return 0;
+    return direct_workspace_floats(length, batch) * sizeof(float);
+}
+
+int haar_direct_1d(const void* x, void* y, int64_t length, int32_t levels, int64_t batch, int32_t dtype,
+                   int32_t inverse, void* workspace, size_t workspace_bytes, void* stream) {
+    if (length < 1) return set_error(HAAR_ERR_SHAPE, "length %lld < 1", (long long)length);
+    bool nothing = false;
+    int rc = check_common(x, y, length, levels, max_levels(length), batch, dtype, &nothing);
+    if (rc != HAAR_OK || nothing) return rc;
+    if (!workspace) return set_error(HAAR_ERR_NULL, "workspace is NULL");
+    if (!aligned(workspace, 4) || workspace_bytes < haar_direct_workspace_size(length, batch))
+        return set_error(HAAR_ERR_WORKSPACE, "workspace misaligned or smaller than %zu bytes",
+                         haar_direct_workspace_size(length, batch));
+    if (rc = fault_injected(); rc != HAAR_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (levels == 0) return copy_levels0(x, y, length * batch * elem_bytes(dtype), s);
+    return run_direct_1d(x, y, length, levels, batch, dtype, inverse != 0, (float*)workspace, s);
+}
+
 const char* haar_status_string(int status) {
     switch (status) {
         case HAAR_OK: return "HAAR_OK";

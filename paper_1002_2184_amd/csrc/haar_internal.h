@@ -39,6 +39,10 @@ constexpr int kShrinkChunk = 4096, kShrinkChunkThreads = 256;
 constexpr int kMaxShrinkLevels2D = 5;
 int run_shrink_1d(const void* in, void* out, int64_t n, int L, int64_t batch, int dtype, int mode,
                   const float* thr, hipStream_t s);
+// Direct (convolve-then-decimate) structure, for comparison with the fast bank.
+size_t direct_workspace_floats(int64_t n, int64_t batch);
+int run_direct_1d(const void* in, void* out, int64_t n, int L, int64_t batch, int dtype, bool inverse,
+                  float* ws, hipStream_t s);
 int run_shrink_2d(const void* in, void* out, int64_t h, int64_t w, int L, int64_t batch, int dtype,
                   int mode, const float* thr, hipStream_t s);
 

@@ -136,6 +136,24 @@ def shrink2d(x: torch.Tensor, levels: int, thresholds, mode: str = "hard",
     return y
 
 
+def direct1d(x: torch.Tensor, levels: int, inverse: bool = False, out: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """The same transform through the direct (convolve-then-decimate) filter
+    bank of Fig. 1 / Fig. 5, one level per pass with the full-rate streams in
+    a workspace; for comparison with fwd1d / inv1d."""
+    x = _prep(x, 1)
+    y = _out(x, out)
+    n = x.shape[-1]
+    batch = x.numel() // n if n > 0 else 0
+    need = _abi.haar_direct_workspace_size(n, batch)
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty(max(need, 4), dtype=torch.uint8, device=x.device)
+    _abi.check(_abi.haar_direct_1d(x.data_ptr(), y.data_ptr(), n, int(levels), batch, dtype_code(x),
+                                   int(inverse), workspace.data_ptr(),
+                                   workspace.numel() * workspace.element_size(), _stream(x.device)))
+    return y
+
+
 def tune_2d(shape, levels: int, dtype=torch.float32, inverse: bool = False, device="cuda") -> int:
     """Time the 2D tile candidates for [batch, h, w] and record the fastest; returns its index."""
     *lead, h, w = shape

@@ -78,6 +78,10 @@ X, Y = 0x10000000, 0x20000000     # fake, non-overlapping device addresses (neve
     (lambda a: a.haar_shrink_2d(X, Y, 64, 64, 6, 1, 0, 0, [1.0] * 6, 0), 9),      # beyond one tile
     (lambda a: a.haar_shrink_2d(X, Y, 8, 8, 4, 1, 0, 0, [1.0] * 4, 0), 4),        # levels > log2
     (lambda a: a.haar_shrink_2d(X, Y, 8, 8, 2, 1, 5, 0, [1.0] * 2, 0), 2),        # dtype
+    (lambda a: a.haar_direct_1d(X, Y, 64, 3, 1, 0, 0, 0, 0, 0), 1),                # no workspace
+    (lambda a: a.haar_direct_1d(X, Y, 64, 3, 1, 0, 0, 0x30000000, 16, 0), 6),      # too small
+    (lambda a: a.haar_direct_1d(X, Y, 64, 3, 1, 0, 0, 0x30000002, 1 << 20, 0), 6), # misaligned
+    (lambda a: a.haar_direct_1d(X, Y, 64, 7, 1, 0, 0, 0x30000000, 1 << 20, 0), 4),  # levels
 ])
 def test_validation_codes(abi, call, code):
     assert call(abi) == code
@@ -98,6 +102,13 @@ def test_shrink_accepts_infinite_threshold(abi, monkeypatch):
     monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")     # valid call, stopped before any HIP call
     assert abi.haar_shrink_2d(X, Y, 64, 64, 2, 1, 0, 1, [float("inf"), 0.0], 0) == 7
     assert abi.haar_shrink_1d(X, Y, 64, 0, 1, 0, 0, None, 0) == 7        # levels 0: a copy
+
+
+def test_direct_workspace_size(abi):
+    # full-rate streams (low-pass as FP32 pairs) plus two pair buffers
+    assert abi.haar_direct_workspace_size(64, 3) == (3 * 3 * 64 + 4 * 3 * 32) * 4
+    assert abi.haar_direct_workspace_size(65, 1) == (3 * 65 + 4 * 33) * 4
+    assert abi.haar_direct_workspace_size(0, 1) == 0
 
 
 def test_batch_zero_is_a_noop(abi):
