@@ -17,11 +17,11 @@
 //   3. the synthesis device code reads the buffer and writes the output.
 // HBM traffic: the input once, the output once.
 //
-// Full 2D tiles take a register path instead: the synthesis of a thread's
-// register block needs exactly the level-1/2 details that the analysis of
-// the same block produced, so those stay in registers (thresholded in
-// place), and only the tile's LL2 region crosses LDS, where one wavefront
-// runs levels 3..L of the analysis, the thresholding and the synthesis.
+// Full 2D tiles and full 1D chunks take register paths instead: the
+// synthesis of a thread's block needs exactly the details that the analysis
+// of the same block produced, so those stay in registers (thresholded in
+// place); only the small deep levels cross LDS (2D: the tile's LL2 region,
+// run by one wavefront; 1D: the levels across wavefronts, on one thread).
 #include "haar_1d_chunk.h"
 #include "haar_2d_tile.h"
 #include "haar_internal.h"
@@ -80,6 +80,143 @@ __global__ __launch_bounds__(NT) void shrink1d_kernel(const void* x, void* y, in
         __syncthreads();
         p.dst = reinterpret_cast<typename S::raw*>(y) + item * n + c0;
         inv1d_chunk<S, StLds, StLds, E, NT, FULL>(p, 0, 0, smf, stage);
+        __syncthreads();                     // LDS reuse by the next chunk
+    }
+}
+
+// Full chunks, register path.  The synthesis of a thread needs exactly the
+// details its own analysis produced (in-thread levels in registers,
+// wavefront levels at the same lanes), so every coefficient stays in
+// registers; only the input / output staging and the levels across
+// wavefronts (at most log2(NT/64), on one thread) use LDS.
+template <class S, int E, int NT>
+__global__ __launch_bounds__(NT) void shrink1d_full_kernel(const void* x, void* y, int64_t n, int L,
+                                                           int64_t per, int64_t total, ShrinkArgs sh) {
+    using G = Geo1D<S, E, NT>;
+    constexpr int C = G::C, LOG_E = G::LOG_E, NW = G::NW;
+    __shared__ float stage[C];
+    __shared__ df sv[NW];
+    __shared__ float sa[NW], sd[NW * 8];
+    __shared__ float thr[kMaxShrinkLevels];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t < kMaxShrinkLevels) thr[t] = sh.thr[t];
+    const int mode = sh.mode;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t item = b / per, c0 = (b - item * per) * C;
+        const typename S::raw* src = reinterpret_cast<const typename S::raw*>(x) + item * n + c0;
+        typename S::raw* dst = reinterpret_cast<typename S::raw*>(y) + item * n + c0;
+
+        float xv[E];
+        ld_chunk_lanes<S, E>(src, stage, xv, lane, wv);
+        df s[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) s[e] = df_from(xv[e]);
+
+        // ---- analysis, in-thread levels: details (thresholded) stay in dl,
+        // level lev at dl[E - (E >> (lev - 1)) + m]
+        float dl[E];
+#pragma unroll
+        for (int lev = 1; lev <= LOG_E; ++lev) {
+            if (lev > L) break;
+            const int cnt = E >> lev;
+            const float tl = sh.thr[lev - 1];
+#pragma unroll
+            for (int m = 0; m < E / 2; ++m) {
+                if (m >= cnt) continue;
+                const df a0 = s[2 * m], a1 = s[2 * m + 1];
+                dl[E - (E >> (lev - 1)) + m] = shrink_value(f_norm(df_diff(a1, a0), lev), mode, tl);
+                s[m] = df_add(a0, a1);
+            }
+        }
+
+        float a[E];
+        if (L <= LOG_E) {
+            const int cnt = E >> L;
+#pragma unroll
+            for (int m = 0; m < E; ++m) a[m] = m < cnt ? df_norm(s[m], L) : 0.0f;
+        } else {
+            // ---- analysis, wavefront levels (active lanes keep the detail)
+            float dw[6];
+            df vv = s[0];
+#pragma unroll
+            for (int st = 0; st < 6; ++st) {
+                const int lev = LOG_E + 1 + st;
+                dw[st] = 0.0f;
+                if (lev > L) continue;
+                const int off = 1 << st;
+                const df o = {__shfl_xor(vv.hi, off), __shfl_xor(vv.lo, off)};
+                if ((lane & ((off << 1) - 1)) == 0) {
+                    dw[st] = shrink_value(f_norm(df_diff(o, vv), lev), mode, sh.thr[lev - 1]);
+                    vv = df_add(vv, o);
+                }
+            }
+            float v = 0.0f;
+            if (L <= LOG_E + 6) {
+                v = df_norm(vv, L);
+            } else {
+                // ---- levels across wavefronts: analysis, threshold, synthesis
+                if (lane == 0) sv[wv] = vv;
+                __syncthreads();
+                if (t == 0) {
+                    constexpr int wtop = LOG_E + 6;
+                    int cnt = NW;
+                    for (int lev = wtop + 1; lev <= L; ++lev) {
+                        for (int P = 0; P < cnt / 2; ++P) {
+                            const df a0 = sv[2 * P], a1 = sv[2 * P + 1];
+                            sd[(lev - wtop - 1) * NW + P] = shrink_value(f_norm(df_diff(a1, a0), lev), mode,
+                                                                         thr[lev - 1]);
+                            sv[P] = df_add(a0, a1);
+                        }
+                        cnt >>= 1;
+                    }
+                    for (int P = 0; P < cnt; ++P) sa[P] = df_norm(sv[P], L);
+                    for (int lev = L; lev >= wtop + 1; --lev) {
+                        const int pairs = (NW >> (lev - wtop - 1)) >> 1;
+                        for (int P = pairs - 1; P >= 0; --P) {
+                            const float aa = sa[P], d = sd[(lev - wtop - 1) * NW + P];
+                            sa[2 * P] = (aa - d) * kRs2Hi;
+                            sa[2 * P + 1] = (aa + d) * kRs2Hi;
+                        }
+                    }
+                }
+                __syncthreads();
+                if (lane == 0) v = sa[wv];
+            }
+            // ---- synthesis, wavefront levels
+#pragma unroll
+            for (int st = 5; st >= 0; --st) {
+                const int lev = LOG_E + 1 + st;
+                if (lev > L) continue;
+                const int off = 1 << st;
+                const bool active = (lane & ((off << 1) - 1)) == 0;
+                float e0 = v, e1 = 0.0f;
+                if (active) {
+                    e0 = (v - dw[st]) * kRs2Hi;
+                    e1 = (v + dw[st]) * kRs2Hi;
+                }
+                const float got = __shfl_xor(e1, off);
+                if (active)
+                    v = e0;
+                else if ((lane & ((off << 1) - 1)) == off)
+                    v = got;
+            }
+            a[0] = v;
+        }
+        // ---- synthesis, in-thread levels
+#pragma unroll
+        for (int lev = LOG_E; lev >= 1; --lev) {
+            if (lev > L) continue;
+            const int cnt = E >> lev;
+            const float* d = dl + (E - (E >> (lev - 1)));
+#pragma unroll
+            for (int m = E / 2 - 1; m >= 0; --m) {
+                if (m >= cnt) continue;
+                const float am = a[m];
+                a[2 * m] = (am - d[m]) * kRs2Hi;
+                a[2 * m + 1] = (am + d[m]) * kRs2Hi;
+            }
+        }
+        st_chunk_lanes<S, E>(dst, stage, a, lane, wv);
         __syncthreads();                     // LDS reuse by the next chunk
     }
 }
@@ -314,7 +451,7 @@ static hipError_t launch_shrink1d(const void* x, void* y, int64_t n, int L, int6
     const int64_t per = n / kShrinkChunk, total = per * batch;
     if (total > 0) {
         const unsigned grid = (unsigned)(total < kMaxGridShrink ? total : kMaxGridShrink);
-        hipLaunchKernelGGL((shrink1d_kernel<S, E, NT, true>), dim3(grid), dim3(NT), 0, s, x, y, n, L, per,
+        hipLaunchKernelGGL((shrink1d_full_kernel<S, E, NT>), dim3(grid), dim3(NT), 0, s, x, y, n, L, per,
                            total, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

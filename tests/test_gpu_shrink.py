@@ -58,8 +58,10 @@ def _check(got, ref, x_rms, dt, what):
     (check_signal if dt == G.F32 else check_lowp_signal)(got, ref, x_rms, dt, what)
 
 
+# full 4096-sample chunks at every kind of depth (in-thread only, wavefront,
+# across wavefronts), ragged tails, and short signals (one partial chunk)
 CASES_1D = [(1, 0), (5, 2), (64, 6), (1000, 3), (4096, 12), (4097, 12), (12345, 5), (65536, 12),
-            (3000, 12)]
+            (3000, 12), (8192, 3), (8192, 8), (16384, 11), (8193, 4)]
 
 
 @pytest.mark.parametrize("dt", [G.F32, G.BF16, G.F16])
