@@ -23,7 +23,9 @@ int device_cus();
 int fault_injected();
 
 // Tile / chunk configuration chosen for a problem (tuning table or default).
-int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels);
+// fallback >= 0: returned when neither a forced choice nor a tuning-table
+// entry exists (plans pass their own default shape).
+int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels, int fallback = -1);
 int choose_config_1d(int dtype, bool inverse, int64_t n, int levels);
 
 int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch, int dtype,

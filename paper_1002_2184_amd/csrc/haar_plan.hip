@@ -410,7 +410,7 @@ int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype,
         return set_error(HAAR_ERR_SHAPE, "plan has too many tiles");
     }
     const int c = choose_config_2d(dtype, inverse != 0, items[order[0]].height, items[order[0]].width,
-                                   items[order[0]].levels);
+                                   items[order[0]].levels, 1);
     pl->cfg = tile_config_2d(eb, c).gx == 32 ? 0 : 1;
     pl->sched = 1;   // 2D tiles differ in cost (edge tiles): claim them
     layout(pl, sizeof(PlanItem2D), pl->items2.size(), sizeof(PlanTile2D),

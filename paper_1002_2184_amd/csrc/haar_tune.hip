@@ -44,15 +44,17 @@ static std::string key_1d(int dtype, bool inverse, int64_t n, int levels) {
     return b;
 }
 
-int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels) {
+int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels, int fallback) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (dtype >= 0 && dtype < 3 && g_force_2d[dtype] >= 0) return g_force_2d[dtype];
     auto it = g_table.find(key_2d(dtype, inverse, h, w, levels));
     if (it != g_table.end()) return it->second;
-    // measured default (4096^2 FP32, 5 levels, cold HBM): 32 x 256 tiles
+    if (fallback >= 0) return fallback;
+    // measured defaults (4096^2, 5 levels, cold HBM): FP32, 32 x 256 tiles
     // (4 x 4 registers per thread, 512 threads), one tile per work-group,
-    // blocks dealt round-robin to the XCDs
-    return 1;
+    // blocks dealt round-robin to the XCDs; 16-bit analysis, the 256-thread
+    // 32 x 256 tiles (19.2 us against 22.0 us for 32 x 512)
+    return (dtype != 0 && !inverse) ? 0 : 1;
 }
 
 int choose_config_1d(int dtype, bool inverse, int64_t n, int levels) {
