@@ -16,6 +16,8 @@ Functions (all float64 in, float64 out, out-of-place, same shape):
   decimate; up-sample, then convolve).
 * ``fwd_2d(x, levels)`` / ``inv_2d(y, levels)`` -- separable 2D on
   ``[..., h, w]``: rows then columns per level, recursion on LL.
+* ``fwd_3d(x, levels)`` / ``inv_3d(y, levels)`` -- separable 3D on
+  ``[..., d, h, w]``: x, then y, then z per level, recursion on LLL.
 * ``filter_taps()`` -- the taps (b0, b1, a0, a1) of Eq. (8), (9), (17), (18).
 """
 from __future__ import annotations
@@ -66,6 +68,10 @@ class Oracle:
         for name in ("oracle_fwd_2d", "oracle_inv_2d"):
             fn = getattr(lib, name)
             fn.argtypes = [P, P, i64, i64, i32, i64]
+            fn.restype = None
+        for name in ("oracle_fwd_3d", "oracle_inv_3d"):
+            fn = getattr(lib, name)
+            fn.argtypes = [P, P, i64, i64, i64, i32, i64]
             fn.restype = None
         lib.oracle_shrink_1d.argtypes = [P, P, i64, i32, i64, i32, P]
         lib.oracle_shrink_1d.restype = None
@@ -121,6 +127,24 @@ class Oracle:
     def inv_2d(self, y, levels):
         """Separable multi-level 2D synthesis on the last two axes."""
         return self._call_2d("oracle_inv_2d", y, levels)
+
+    def _call_3d(self, name, x, levels):
+        _check_levels(levels)
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        if x.ndim < 3 or min(x.shape[-3:]) < 1:
+            raise ValueError("3D oracle needs non-empty last three axes")
+        d, h, w = x.shape[-3], x.shape[-2], x.shape[-1]
+        y = np.empty_like(x)
+        getattr(self.lib, name)(_ptr(x), _ptr(y), d, h, w, int(levels), x.size // (d * h * w))
+        return y
+
+    def fwd_3d(self, x, levels):
+        """Separable multi-level 3D analysis on the last three axes (x, y, z per level)."""
+        return self._call_3d("oracle_fwd_3d", x, levels)
+
+    def inv_3d(self, y, levels):
+        """Separable multi-level 3D synthesis (z, y, x per level, levels L..1)."""
+        return self._call_3d("oracle_inv_3d", y, levels)
 
     def _thresholds(self, levels, thresholds):
         t = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float64).reshape(-1))
@@ -196,6 +220,34 @@ def fwd_2d(x, levels: int) -> np.ndarray:
 
 def inv_2d(y, levels: int) -> np.ndarray:
     return default().inv_2d(y, levels)
+
+
+def fwd_3d(x, levels: int) -> np.ndarray:
+    return default().fwd_3d(x, levels)
+
+
+def inv_3d(y, levels: int) -> np.ndarray:
+    return default().inv_3d(y, levels)
+
+
+def band_slices_3d(d: int, h: int, w: int, levels: int):
+    """3D packed layout: {'LLL': (z, y, x slices), (code, j): ...} where code
+    is a 3-letter string of L/H for the (x, y, z) filters, e.g. 'HLL' = high
+    along x only."""
+    ds, hs, ws = sizes_1d(d, levels), sizes_1d(h, levels), sizes_1d(w, levels)
+    sl = {"LLL": (slice(0, ds[levels]), slice(0, hs[levels]), slice(0, ws[levels]))}
+    for j in range(1, levels + 1):
+        for bz in (0, 1):
+            for by in (0, 1):
+                for bx in (0, 1):
+                    if bx == by == bz == 0:
+                        continue
+                    zs = slice(ds[j], ds[j - 1]) if bz else slice(0, ds[j])
+                    ys = slice(hs[j], hs[j - 1]) if by else slice(0, hs[j])
+                    xs = slice(ws[j], ws[j - 1]) if bx else slice(0, ws[j])
+                    code = ("H" if bx else "L") + ("H" if by else "L") + ("H" if bz else "L")
+                    sl[(code, j)] = (zs, ys, xs)
+    return sl
 
 
 def shrink_1d(x, levels: int, mode: int, thresholds) -> np.ndarray:

@@ -40,6 +40,10 @@
  *   - odd lengths ("carry rule"): when a level sees an odd count, its last
  *     sample passes unscaled into the approximation; there is no detail
  *     for it.  ceil(n/2) approximations, floor(n/2) details.
+ *   - 3D (volumes [batch][d][h][w], the paper's medical-image use): the 2D
+ *     reading extended by one axis; per level one 1D level along x (width),
+ *     then y (height), then z (depth) on the current LLL region, recursion
+ *     on LLL; eight octant bands named by their (x, y, z) filters.
  */
 #include <math.h>
 #include <stdint.h>
@@ -318,6 +322,73 @@ void oracle_inv_2d(const double* y, double* x, int64_t h, int64_t w,
 {
     for (int64_t b = 0; b < batch; ++b)
         inv_2d_item(y + b * h * w, x + b * h * w, h, w, levels);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Separable 3D (volumes): per level, a 1D level along every x line (width)  */
+/* of the current LLL region, then along every y line (height), then along */
+/* every z line (depth); the next level works on the LLL octant            */
+/* [0, ceil(d/2)) x [0, ceil(h/2)) x [0, ceil(w/2)).  The synthesis runs z, */
+/* y, x per level, levels L..1.  Layout [batch][d][h][w].                  */
+/* ---------------------------------------------------------------------- */
+static void lines_3d(double* v, int64_t h, int64_t w, int64_t cd, int64_t ch,
+                     int64_t cw, int axis, int inverse)
+{
+    /* axis 0: x lines (length cw), 1: y lines (ch), 2: z lines (cd) */
+    const int64_t len = axis == 0 ? cw : (axis == 1 ? ch : cd);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? w : h * w);
+    const int64_t na = axis == 0 ? cd * ch : (axis == 1 ? cd * cw : ch * cw);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < na; ++q) {
+        int64_t base;
+        if (axis == 0)      base = (q / ch) * h * w + (q % ch) * w;          /* (z, y) */
+        else if (axis == 1) base = (q / cw) * h * w + (q % cw);              /* (z, x) */
+        else                base = (q / cw) * w + (q % cw);                  /* (y, x) */
+        double* tmp = (double*)malloc((size_t)len * sizeof(double));
+        for (int64_t k = 0; k < len; ++k) tmp[k] = v[base + k * stride];
+        if (inverse) fast_synthesis_level(tmp, 1, v + base, stride, len);
+        else         fast_analysis_level(tmp, 1, v + base, stride, len);
+        free(tmp);
+    }
+}
+
+void oracle_fwd_3d(const double* x, double* y, int64_t d, int64_t h, int64_t w,
+                   int32_t levels, int64_t batch)
+{
+    for (int64_t b = 0; b < batch; ++b) {
+        double* v = y + b * d * h * w;
+        memcpy(v, x + b * d * h * w, (size_t)(d * h * w) * sizeof(double));
+        int64_t cd = d, ch = h, cw = w;
+        for (int j = 1; j <= levels; ++j) {
+            lines_3d(v, h, w, cd, ch, cw, 0, 0);
+            lines_3d(v, h, w, cd, ch, cw, 1, 0);
+            lines_3d(v, h, w, cd, ch, cw, 2, 0);
+            cd = (cd + 1) / 2;
+            ch = (ch + 1) / 2;
+            cw = (cw + 1) / 2;
+        }
+    }
+}
+
+void oracle_inv_3d(const double* y, double* x, int64_t d, int64_t h, int64_t w,
+                   int32_t levels, int64_t batch)
+{
+    int64_t ld[64], lh[64], lw[64];
+    ld[0] = d; lh[0] = h; lw[0] = w;
+    for (int j = 1; j <= levels; ++j) {
+        ld[j] = (ld[j - 1] + 1) / 2;
+        lh[j] = (lh[j - 1] + 1) / 2;
+        lw[j] = (lw[j - 1] + 1) / 2;
+    }
+    for (int64_t b = 0; b < batch; ++b) {
+        double* v = x + b * d * h * w;
+        memcpy(v, y + b * d * h * w, (size_t)(d * h * w) * sizeof(double));
+        for (int j = levels; j >= 1; --j) {
+            lines_3d(v, h, w, ld[j - 1], lh[j - 1], lw[j - 1], 2, 1);
+            lines_3d(v, h, w, ld[j - 1], lh[j - 1], lw[j - 1], 1, 1);
+            lines_3d(v, h, w, ld[j - 1], lh[j - 1], lw[j - 1], 0, 1);
+        }
+    }
 }
 
 /* ---------------------------------------------------------------------- */

@@ -1,7 +1,7 @@
 """Pins of the FP64 oracle against what the paper and the mathematics fix.
 
 Each ``pin_*`` takes an oracle object (``oracle.Oracle``: fwd_1d, inv_1d,
-direct_fwd_1d, direct_inv_1d, fwd_2d, inv_2d, filter_taps) and raises
+direct_fwd_1d, direct_inv_1d, fwd_2d, inv_2d, fwd_3d, inv_3d, filter_taps) and raises
 AssertionError when it disagrees.  None of them re-types the oracle's loops:
 they compare it with closed forms, hand-derived fixtures, an independent
 formulation (the direct filter bank), polynomial identities of the filter
@@ -369,9 +369,103 @@ def pin_shrink_hard_projection(orc):
     _close(orc.shrink_2d(once2, 3, 0, t2), once2, 1e-12, "2D hard twice")
 
 
+# ---------------------------------------------------------------------------
+# Separable 3D (volumes [d][h][w]; per level x, then y, then z on LLL).
+
+
+def _bands3_expected(orc, u, v, w, L):
+    """Packed 3D transform of the rank-1 volume u (x) v (x) w (z, y, x) from
+    1D transforms: band (x, y, z filters) at level j is the outer product of
+    a_j or d_j of each factor, LLL_L = a_L(u) a_L(v) a_L(w)."""
+    d, h, wd = len(u), len(v), len(w)
+    if L == 0:
+        return np.einsum("i,j,k->ijk", u, v, w)
+    ds, hs, ws = sizes(d, L), sizes(h, L), sizes(wd, L)
+    exp = np.zeros((d, h, wd))
+    au, av, aw = (orc.fwd_1d(t, L)[:sizes(len(t), L)[L]] for t in (u, v, w))
+    exp[:ds[L], :hs[L], :ws[L]] = np.einsum("i,j,k->ijk", au, av, aw)
+    for j in range(1, L + 1):
+        pu, pv, pw = _bands_1d(orc, u, j), _bands_1d(orc, v, j), _bands_1d(orc, w, j)
+        for bz in (0, 1):
+            for by in (0, 1):
+                for bx in (0, 1):
+                    if bx == by == bz == 0:
+                        continue
+                    zs = slice(ds[j], ds[j - 1]) if bz else slice(0, ds[j])
+                    ys = slice(hs[j], hs[j - 1]) if by else slice(0, hs[j])
+                    xs = slice(ws[j], ws[j - 1]) if bx else slice(0, ws[j])
+                    exp[zs, ys, xs] = np.einsum("i,j,k->ijk", pu[bz], pv[by], pw[bx])
+    return exp
+
+
+def pin_3d_separable(orc):
+    """Rank-1 volumes u (x) v (x) w: every 3D band is an outer product of the
+    1D bands of the factors, at every level and for odd sizes (carries on
+    each axis); impulses e_p (x) e_q (x) e_r pin the operator entry by entry.
+    The inverse maps the expected bands back to the volume."""
+    rng = np.random.default_rng(23)
+    shapes = [(1, 1, 1), (1, 1, 6), (1, 5, 1), (7, 1, 1), (2, 2, 2), (3, 5, 7), (8, 8, 8),
+              (5, 9, 4), (9, 6, 11), (16, 4, 12)]
+    for (d, h, w) in shapes:
+        for L in range(0, max_levels(max(d, h, w)) + 1):
+            for trial in range(2):
+                if trial == 0:
+                    u, v, t = np.zeros(d), np.zeros(h), np.zeros(w)
+                    u[rng.integers(d)] = 1.0
+                    v[rng.integers(h)] = 1.0
+                    t[rng.integers(w)] = 1.0
+                else:
+                    u, v, t = rng.standard_normal(d), rng.standard_normal(h), rng.standard_normal(w)
+                x = np.einsum("i,j,k->ijk", u, v, t)
+                exp = _bands3_expected(orc, u, v, t, L)
+                _close(orc.fwd_3d(x, L), exp, 1e-13, f"3D rank-1 {d}x{h}x{w} L={L}")
+                _close(orc.inv_3d(exp, L), x, 1e-13, f"3D rank-1 inverse {d}x{h}x{w} L={L}")
+
+
+def pin_3d_reductions(orc):
+    """A volume of depth 1 is an image (the 3D transform reduces to the 2D
+    one); a volume of one row and one column is a 1D signal along z."""
+    rng = np.random.default_rng(29)
+    for (h, w, L) in [(7, 9, 3), (16, 12, 2), (5, 33, 5)]:
+        x = rng.standard_normal((2, h, w))
+        _close(orc.fwd_3d(x[:, None], L)[:, 0], orc.fwd_2d(x, L), 1e-15, f"3D depth 1 {h}x{w}")
+        _close(orc.inv_3d(x[:, None], L)[:, 0], orc.inv_2d(x, L), 1e-15, f"3D inv depth 1 {h}x{w}")
+    for (d, L) in [(13, 3), (64, 6)]:
+        x = rng.standard_normal((2, d))
+        _close(orc.fwd_3d(x[:, :, None, None], L)[:, :, 0, 0], orc.fwd_1d(x, L), 1e-15, f"3D z line {d}")
+        _close(orc.inv_3d(x[:, :, None, None], L)[:, :, 0, 0], orc.inv_1d(x, L), 1e-15, f"3D inv z {d}")
+
+
+def pin_3d_invariants(orc):
+    """Constant volumes (2^L | d, h, w): zero details, LLL_L = c 2^(3L/2).
+    Orthonormality of the full matrix on small odd volumes; Parseval and
+    perfect reconstruction on random volumes."""
+    c = -1.75
+    for (d, h, w, L) in [(8, 8, 8, 3), (4, 16, 32, 2), (16, 16, 16, 4)]:
+        y = orc.fwd_3d(np.full((d, h, w), c), L)
+        dL, hL, wL = d >> L, h >> L, w >> L
+        _close(y[:dL, :hL, :wL], np.full((dL, hL, wL), c * 2.0 ** (1.5 * L)), 1e-15, "3D const LLL")
+        mask = np.ones((d, h, w), bool)
+        mask[:dL, :hL, :wL] = False
+        assert np.all(y[mask] == 0.0), f"3D const details {d}x{h}x{w}"
+    for (d, h, w, L) in [(3, 4, 5, 2), (2, 3, 2, 1), (5, 3, 3, 3)]:
+        n = d * h * w
+        M = orc.fwd_3d(np.eye(n).reshape(n, d, h, w), L).reshape(n, n).T
+        _close(M @ M.T, np.eye(n), 1e-14, f"3D orthonormal {d}x{h}x{w}")
+        Mi = orc.inv_3d(np.eye(n).reshape(n, d, h, w), L).reshape(n, n).T
+        _close(Mi, M.T, 1e-14, f"3D synthesis = analysis^T {d}x{h}x{w}")
+    rng = np.random.default_rng(31)
+    for (d, h, w, L) in [(9, 17, 33, 4), (32, 16, 64, 3), (6, 6, 130, 2)]:
+        x = rng.standard_normal((2, d, h, w))
+        y = orc.fwd_3d(x, L)
+        _close(np.sum(y * y, (1, 2, 3)), np.sum(x * x, (1, 2, 3)), 1e-13, "3D Parseval")
+        _close(orc.inv_3d(y, L), x, 1e-13, f"3D PR {d}x{h}x{w}")
+
+
 ALL_PINS = [
     pin_paper_coefficients, pin_worked_examples, pin_dyadic_closed_form, pin_carry_weights,
     pin_carry_impulse, pin_orthonormal_and_inverse, pin_direct_equals_fast, pin_alias_free_taps,
     pin_constant, pin_parseval_and_pr, pin_2d_separable, pin_2d_dyadic_closed_form,
     pin_locality, pin_adjoint, pin_shrink_matrix, pin_shrink_extremes, pin_shrink_hard_projection,
+    pin_3d_separable, pin_3d_reductions, pin_3d_invariants,
 ]

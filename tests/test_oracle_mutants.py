@@ -61,6 +61,14 @@ MUTANTS = {
     "shrink_2d_only_hh": ("if (r >= lh[j] || q >= lw[j])", "if (r >= lh[j] && q >= lw[j])"),
     "2d_row_skips_last": ("for (int64_t r = 0; r < ch; ++r) {            /* rows (width)   */",
                           "for (int64_t r = 0; r < ch - 1; ++r) {            /* rows (width)   */"),
+    "3d_depth_floor": ("cd = (cd + 1) / 2;", "cd = cd / 2;"),
+    "3d_z_pass_skipped": ("lines_3d(v, h, w, cd, ch, cw, 2, 0);", "/* z pass dropped */"),
+    "3d_inverse_sizes": ("ld[j] = (ld[j - 1] + 1) / 2;", "ld[j] = ld[j - 1] / 2;"),
+    "3d_inverse_y_skipped": ("lines_3d(v, h, w, ld[j - 1], lh[j - 1], lw[j - 1], 1, 1);", "/* y pass dropped */"),
+    "3d_y_lines_plane_stride_as_row": ("else if (axis == 1) base = (q / cw) * h * w + (q % cw);",
+                               "else if (axis == 1) base = (q / cw) * w + (q % cw);"),
+    "3d_inverse_region_one_level_late": ("lines_3d(v, h, w, ld[j - 1], lh[j - 1], lw[j - 1], 2, 1);",
+                                         "lines_3d(v, h, w, ld[j - 1], lh[j], lw[j - 1], 2, 1);"),
 }
 
 
