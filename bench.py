@@ -374,6 +374,36 @@ def suite():
     res["note"] = "GB/s = algorithmic bytes (read + write once) / time"
     print(json.dumps(res), flush=True)
 
+    # 8) separable 3D on CT-like volumes: 4 x 256^3, 3 levels (one fused
+    #    pass) in FP32 and BF16, and full depth (8 levels, three passes)
+    vol = torch.from_numpy(G.to_storage(G.phantom_volume(G.rng_for(8), 256, 256, 256), G.F32)).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(G.SEED + 8)
+    for dt, L in ((torch.float32, 3), (torch.bfloat16, 3), (torch.float32, 8)):
+        vs = [(vol + 0.02 * torch.randn((4, 256, 256, 256), device=dev, generator=gen)).to(dt) for _ in range(4)]
+        cs = [torch.empty_like(v) for v in vs]
+        nb = 2 * vs[0].numel() * vs[0].element_size()
+        kk[0] = 0
+
+        def vf():
+            k = kk[0] = (kk[0] + 1) % 4
+            T.fwd3d(vs[k], L, out=cs[k])
+
+        def vi():
+            k = kk[0] = (kk[0] + 1) % 4
+            T.inv3d(cs[k], L, out=vs[(k + 2) % 4])
+
+        def vc():
+            k = kk[0] = (kk[0] + 1) % 4
+            cs[k].copy_(vs[k])
+        res = {"workload": f"3d-phantom-4x256^3-L{L} {str(dt).split('.')[-1]}"}
+        for name, fn in (("fwd", vf), ("inv", vi), ("torch_copy", vc)):
+            ms = _timed(fn, 20, 4, st)
+            res[f"us_{name}"] = round(ms * 1e3, 2)
+            res[f"gbps_{name}"] = round(nb / (ms * 1e-3) / 1e9, 1)
+        print(json.dumps(res), flush=True)
+        del vs, cs
+
 
 def cpu_baseline(x_np, budget_s: float):
     """The FP64 oracle (fwd + inv of the same image) on this host's cores."""

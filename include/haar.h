@@ -43,8 +43,9 @@
  *   haar_last_error() holds a message (thread-local).
  * Aliasing.  Out-of-place only: overlapping input and output ranges return
  *   HAAR_ERR_ALIAS (the fused tiles write into other tiles' input ranges).
- * Levels.  0 <= levels <= haar_max_levels_1d(length) (1D) or
- *   haar_max_levels_2d(height, width) (2D); levels = 0 copies.  batch = 0
+ * Levels.  0 <= levels <= haar_max_levels_1d(length) (1D),
+ *   haar_max_levels_2d(height, width) (2D) or haar_max_levels_3d (3D);
+ *   levels = 0 copies.  batch = 0
  *   enqueues nothing and returns HAAR_OK.
  * Threading.  All entry points are reentrant; the tuning table is guarded by
  *   a mutex.
@@ -118,6 +119,28 @@ int haar_fwd_2d(const void* x, void* y, int64_t height, int64_t width,
 int haar_inv_2d(const void* y, void* x, int64_t height, int64_t width,
                 int32_t levels, int64_t batch, int32_t dtype, void* stream);
 
+/* Multi-level separable 3D analysis of volumes (the paper's medical-image
+ * application, Sec. I and Sec. V, carried to three axes): per level one 1D
+ * level (Sec. III, Eq. (11)-(12), Fig. 4) along every x line (width), then
+ * every y line (height), then every z line (depth) of the current LLL
+ * region; recursion on LLL.  x: [batch][depth][height][width], y: same
+ * shape, packed octant layout: after level j the region D_{j-1} x H_{j-1} x
+ * W_{j-1} is split at D_j = ceil(D_{j-1}/2), H_j, W_j, and the octant that
+ * is high-pass along a set of axes lies on the high side of those axes.
+ * Odd counts carry their last sample unscaled on each axis.  Three levels
+ * are fused per pass; deeper transforms allocate stream-ordered scratch of
+ * 8 bytes per element of the level-3 LLL region (twice). */
+int haar_fwd_3d(const void* x, void* y, int64_t depth, int64_t height,
+                int64_t width, int32_t levels, int64_t batch, int32_t dtype,
+                void* stream);
+
+/* Multi-level separable 3D synthesis (Sec. IV, Eq. (19), Fig. 7 along z,
+ * then y, then x per level, levels L..1): exact inverse and adjoint of
+ * haar_fwd_3d.  y: packed coefficients, x: reconstruction, same shape. */
+int haar_inv_3d(const void* y, void* x, int64_t depth, int64_t height,
+                int64_t width, int32_t levels, int64_t batch, int32_t dtype,
+                void* stream);
+
 /* ------------------------------------------------------------------------
  * Fused shrinkage: analysis, thresholding of the detail coefficients,
  * synthesis, in ONE pass over HBM (each element is read once and written
@@ -182,6 +205,9 @@ int haar_max_levels_1d(int64_t length);
 
 /* ceil(log2(max(height, width))); -1 if a size < 1. */
 int haar_max_levels_2d(int64_t height, int64_t width);
+
+/* ceil(log2(max(depth, height, width))); -1 if a size < 1. */
+int haar_max_levels_3d(int64_t depth, int64_t height, int64_t width);
 
 /* ------------------------------------------------------------------------
  * Batched transforms of uneven sizes (many signals or images of different

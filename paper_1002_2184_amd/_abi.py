@@ -46,12 +46,15 @@ _SIGS = {
     "haar_inv_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_fwd_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_inv_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
+    "haar_fwd_3d": ([_VP, _VP, _I64, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
+    "haar_inv_3d": ([_VP, _VP, _I64, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_shrink_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _I32, _FP, _VP], ctypes.c_int),
     "haar_shrink_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _I32, _FP, _VP], ctypes.c_int),
     "haar_direct_workspace_size": ([_I64, _I64], ctypes.c_size_t),
     "haar_direct_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _I32, _VP, _SZ, _VP], ctypes.c_int),
     "haar_max_levels_1d": ([_I64], ctypes.c_int),
     "haar_max_levels_2d": ([_I64, _I64], ctypes.c_int),
+    "haar_max_levels_3d": ([_I64, _I64, _I64], ctypes.c_int),
     "haar_plan_create_1d": ([ctypes.POINTER(Item1D), _I64, _I32, _I32, ctypes.POINTER(_VP)], ctypes.c_int),
     "haar_plan_create_2d": ([ctypes.POINTER(Item2D), _I64, _I32, _I32, ctypes.POINTER(_VP)], ctypes.c_int),
     "haar_plan_workspace_size": ([_VP, ctypes.POINTER(_SZ)], ctypes.c_int),
@@ -116,6 +119,14 @@ def haar_inv_2d(y, x, height, width, levels, batch, dtype, stream=0):
     return lib().haar_inv_2d(y, x, height, width, levels, batch, dtype, stream)
 
 
+def haar_fwd_3d(x, y, depth, height, width, levels, batch, dtype, stream=0):
+    return lib().haar_fwd_3d(x, y, depth, height, width, levels, batch, dtype, stream)
+
+
+def haar_inv_3d(y, x, depth, height, width, levels, batch, dtype, stream=0):
+    return lib().haar_inv_3d(y, x, depth, height, width, levels, batch, dtype, stream)
+
+
 def haar_shrink_1d(x, y, length, levels, batch, dtype, mode, thresholds, stream=0):
     """thresholds: a sequence of `levels` floats (copied into a host array)."""
     return lib().haar_shrink_1d(x, y, length, levels, batch, dtype, mode, _floats(thresholds), stream)
@@ -148,6 +159,10 @@ def haar_max_levels_1d(length):
 
 def haar_max_levels_2d(height, width):
     return lib().haar_max_levels_2d(height, width)
+
+
+def haar_max_levels_3d(depth, height, width):
+    return lib().haar_max_levels_3d(depth, height, width)
 
 
 def haar_plan_create_1d(items, count, dtype, inverse, out_ptr):

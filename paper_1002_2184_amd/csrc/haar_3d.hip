@@ -1,0 +1,844 @@
+// Separable 3D Haar transform of volumes [batch][d][h][w], the paper's
+// medical-image use carried to volumetric data.  One level applies the fast
+// analysis bank (Sec. III, Eq. (11)-(12), Fig. 4) along every x line
+// (width), then every y line (height), then every z line (depth) of the
+// current LLL region; the next level recurses on the LLL octant.  Synthesis
+// (Sec. IV, Eq. (19), Fig. 7) undoes the three axes in reverse, levels L..1.
+// Odd counts follow the carry rule of the 1D bank on each axis.
+//
+// Packed layout: after level j the region [0, D_{j-1}) x [0, H_{j-1}) x
+// [0, W_{j-1}) holds eight octants split at D_j = ceil(D_{j-1}/2) (and H_j,
+// W_j); octant (bx, by, bz) holds the band that is high-pass along the axes
+// whose bit is set.
+//
+// One work-group owns a tile of 8 x 8 x 64 samples (z, y, x; interior
+// tiles of 16-bit data are 128 wide), so a pass fuses three levels.  Interior tiles of a storage-typed region run the
+// register path: level 1 inside each thread (2 x 2 x 2 blocks), level 2
+// across lanes with shuffles, level 3 on one wavefront through LDS.  Edge
+// tiles, odd counts and the passes that start from scratch run a generic
+// path that keeps the tile in LDS as compensated pairs.  Deeper transforms
+// chain passes through compensated FP32 scratch.
+#include <vector>
+
+#include "haar.h"
+#include "haar_device.h"
+#include "haar_internal.h"
+
+namespace haar {
+
+namespace {
+
+constexpr int kTZ = 8, kTY = 8, kTX = 64;       // generic tile
+constexpr int kMaxPassLevels3D = 3;            // log2 of the tile's shortest side
+constexpr int kTile = kTZ * kTY * kTX;         // 4096 samples
+constexpr int kThreads3 = 256;
+// (1/sqrt2)^3 = 1/(2 sqrt2) as a pair; halving the 1/sqrt2 pair is exact
+constexpr float kC3Hi = kRs2Hi * 0.5f;
+constexpr float kC3Lo = kRs2Lo * 0.5f;
+
+struct Pass3D {
+    // analysis: src (region) -> det (bands) + ll (deepest LLL of the pass)
+    // synthesis: ll + det -> dst (region)
+    // Strides in elements: plane (z), row (y), item (batch).
+    const void* src; int64_t src_p, src_r, src_b;
+    void* dst;       int64_t dst_p, dst_r, dst_b;
+    void* ll;        int64_t ll_p, ll_r, ll_b;
+    void* det;       int64_t det_p, det_r, det_b;
+    int64_t d, h, w, batch;                    // region of this pass
+    int32_t levels;                            // 1..3
+    int64_t ntz, nty, ntx;                     // tiles per axis
+    int64_t fz, fy, fx;                        // interior tiles per axis (register path)
+    int64_t cx0, ncx;                          // x where interior tiles end; generic tiles after it
+    int64_t nfull, nedge;                      // interior / other tiles, all items
+};
+
+__device__ __forceinline__ df df_neg(df a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ df df_sub(df a, df b) { return df_add(a, df_neg(b)); }
+__device__ __forceinline__ df df_c3(df a) { return df_mul(a, kC3Hi, kC3Lo); }
+
+// Value access of a region, LLL or scratch buffer: storage type S, or
+// compensated pairs (DF) in scratch.
+template <class S, bool DF>
+__device__ __forceinline__ df ld_val(const void* base, int64_t i) {
+    if constexpr (DF)
+        return reinterpret_cast<const df*>(base)[i];
+    else
+        return df_from(S::ld(reinterpret_cast<const typename S::raw*>(base)[i]));
+}
+
+template <class S, bool DF>
+__device__ __forceinline__ void st_val(void* base, int64_t i, df v) {
+    if constexpr (DF)
+        reinterpret_cast<df*>(base)[i] = v;
+    else
+        st1_cached<S>(reinterpret_cast<typename S::raw*>(base) + i, df_round(v));
+}
+
+// Butterflies over the three axes of a 2 x 2 x 2 block, index dx | dy<<1 |
+// dz<<2.  Analysis leaves at index c the unscaled coefficient that is
+// high-pass along the axes whose bit is set in c (pair: (v0 + v1, v1 - v0));
+// synthesis applies the transposed stages ((a - d, a + d)).  Multiplying by
+// 1/(2 sqrt2) gives the orthonormal values.
+template <bool INV>
+__device__ __forceinline__ void bfly8(float* q) {
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!(i & bit)) {
+                const float a = q[i], b = q[i | bit];
+                q[i] = INV ? a - b : a + b;
+                q[i | bit] = INV ? a + b : b - a;
+            }
+}
+
+template <bool INV>
+__device__ __forceinline__ void bfly8_df(df* q) {
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!(i & bit)) {
+                const df a = q[i], b = q[i | bit];
+                q[i] = INV ? df_sub(a, b) : df_add(a, b);
+                q[i | bit] = INV ? df_add(a, b) : df_sub(b, a);
+            }
+}
+
+__device__ __forceinline__ df shfl_xor_pair(df a, int m) {
+    return df{__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)};
+}
+
+// Sizes of the LLL region after level j of the pass; the high halves of the
+// level-j octants start there on each axis.
+struct Level3 {
+    int64_t D, H, W;
+};
+
+__device__ __forceinline__ Level3 level_sizes(const Pass3D& p, int j) {
+    return {ceil_shift(p.d, j), ceil_shift(p.h, j), ceil_shift(p.w, j)};
+}
+
+// ---------------------------------------------------------------------------
+// Generic path: the tile in LDS as pairs, one 1D level per axis and level.
+// ---------------------------------------------------------------------------
+
+// One analysis (INV = false) or synthesis level along axis A (0 x, 1 y, 2 z)
+// on every line of the local region [0, nz) x [0, ny) x [0, nx) in sm.  The
+// 2048 (line, pair) slots of a full tile are dealt 8 per thread; the values
+// are read into registers, then written back after a barrier.
+template <int A, bool INV>
+__device__ __forceinline__ void lds_level(df* sm, int nz, int ny, int nx) {
+    const int n = A == 0 ? nx : (A == 1 ? ny : nz);
+    const int pairs = n >> 1, na = n - pairs;
+    constexpr int st = A == 0 ? 1 : (A == 1 ? kTX : kTX * kTY);
+    df u[8], v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int i = threadIdx.x + kThreads3 * k;
+        int z, y, x, m;
+        if (A == 0) { m = i & 31; y = (i >> 5) & 7; z = i >> 8; x = 0; }
+        else if (A == 1) { x = i & 63; m = (i >> 6) & 3; z = i >> 8; y = 0; }
+        else { x = i & 63; y = (i >> 6) & 7; m = i >> 9; z = 0; }
+        const bool act = m < na && z < nz && y < ny && x < nx;
+        const int b = (z * kTY + y) * kTX + x;
+        if (act) {
+            if (m < pairs) {
+                if (!INV) {
+                    const df x0 = sm[b + 2 * m * st], x1 = sm[b + (2 * m + 1) * st];
+                    u[k] = df_rs2(df_add(x0, x1));            // Eq. (11)
+                    v[k] = df_rs2(df_sub(x1, x0));            // Eq. (12)
+                } else {
+                    const df a = sm[b + m * st], d = sm[b + (na + m) * st];
+                    u[k] = df_rs2(df_sub(a, d));              // Eq. (19), even phase
+                    v[k] = df_rs2(df_add(a, d));              // odd phase
+                }
+            } else {
+                u[k] = INV ? sm[b + (na - 1) * st] : sm[b + (n - 1) * st];   // carry
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int i = threadIdx.x + kThreads3 * k;
+        int z, y, x, m;
+        if (A == 0) { m = i & 31; y = (i >> 5) & 7; z = i >> 8; x = 0; }
+        else if (A == 1) { x = i & 63; m = (i >> 6) & 3; z = i >> 8; y = 0; }
+        else { x = i & 63; y = (i >> 6) & 7; m = i >> 9; z = 0; }
+        const bool act = m < na && z < nz && y < ny && x < nx;
+        const int b = (z * kTY + y) * kTX + x;
+        if (act) {
+            if (m < pairs) {
+                if (!INV) {
+                    sm[b + m * st] = u[k];
+                    sm[b + (na + m) * st] = v[k];
+                } else {
+                    sm[b + 2 * m * st] = u[k];
+                    sm[b + (2 * m + 1) * st] = v[k];
+                }
+            } else {
+                if (!INV) sm[b + m * st] = u[k];
+                else sm[b + (n - 1) * st] = u[k];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Local sample counts of a tile: the tile holds c samples of the region on
+// an axis, hence ceil(c / 2^j) samples of the level-j LLL region (tile
+// origins are multiples of 2^3).
+struct Counts3 {
+    int z, y, x;                               // samples of the region in the tile
+    __device__ __forceinline__ int cz(int j) const { return (z + (1 << j) - 1) >> j; }
+    __device__ __forceinline__ int cy(int j) const { return (y + (1 << j) - 1) >> j; }
+    __device__ __forceinline__ int cx(int j) const { return (x + (1 << j) - 1) >> j; }
+};
+
+__device__ __forceinline__ Counts3 tile_counts(const Pass3D& p, int64_t oz, int64_t oy, int64_t ox) {
+    return {(int)min<int64_t>(kTZ, p.d - oz), (int)min<int64_t>(kTY, p.h - oy),
+            (int)min<int64_t>(kTX, p.w - ox)};
+}
+
+// Global position in the packed volume of local element (z, y, x) of the
+// level-j octants of a tile at origin (oz, oy, ox): low half at o/2^j + l,
+// high half at {D,H,W}_j + o/2^j + (l - a).
+__device__ __forceinline__ int64_t band_pos(int l, int a, int64_t o, int j, int64_t N) {
+    return l < a ? (o >> j) + l : N + (o >> j) + (l - a);
+}
+
+// The 4096 positions of a tile, 16 per thread, x fastest.  Loops over them
+// are unrolled so that a thread's global loads are all in flight before the
+// first use (one HBM latency per phase instead of one per element).
+constexpr int kPerThread3 = kTile / kThreads3;
+
+struct TilePos {
+    int i, z, y, x;
+};
+
+__device__ __forceinline__ TilePos tile_pos(int k) {
+    const int i = threadIdx.x + kThreads3 * k;
+    return {i, i >> 9, (i >> 6) & 7, i & 63};
+}
+
+// Detail octants of level j between LDS and the packed volume.
+template <class S, bool LOAD>
+__device__ __forceinline__ void lds_details(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
+                                            int64_t ox, const Counts3& c, int j, df* sm) {
+    const Level3 L = level_sizes(p, j);
+    const int nz = c.cz(j - 1), ny = c.cy(j - 1), nx = c.cx(j - 1);
+    const int az = c.cz(j), ay = c.cy(j), ax = c.cx(j);
+    using raw = typename S::raw;
+    raw* det = reinterpret_cast<raw*>(p.det) + item * p.det_b;
+    float r[kPerThread3];
+#pragma unroll
+    for (int k = 0; k < kPerThread3; ++k) {
+        const TilePos t = tile_pos(k);
+        const bool in = t.z < nz && t.y < ny && t.x < nx && !(t.z < az && t.y < ay && t.x < ax);
+        if (!in) continue;
+        const int64_t g = band_pos(t.z, az, oz, j, L.D) * p.det_p + band_pos(t.y, ay, oy, j, L.H) * p.det_r +
+                          band_pos(t.x, ax, ox, j, L.W);
+        if (LOAD)
+            r[k] = ld1<S>(det + g);
+        else
+            st1_cached<S>(det + g, df_round(sm[t.i]));
+    }
+    if (LOAD) {
+#pragma unroll
+        for (int k = 0; k < kPerThread3; ++k) {
+            const TilePos t = tile_pos(k);
+            if (t.z < nz && t.y < ny && t.x < nx && !(t.z < az && t.y < ay && t.x < ax))
+                sm[t.i] = df_from(r[k]);
+        }
+    }
+}
+
+// Tile box [0, bz) x [0, by) x [0, bx) from a buffer (origin b, plane and row
+// strides) into LDS.
+template <class S, bool DF>
+__device__ __forceinline__ void lds_fill(df* sm, const void* src, int64_t b, int64_t sp, int64_t sr, int bz,
+                                         int by, int bx) {
+    df r[kPerThread3];
+#pragma unroll
+    for (int k = 0; k < kPerThread3; ++k) {
+        const TilePos t = tile_pos(k);
+        if (t.z < bz && t.y < by && t.x < bx) r[k] = ld_val<S, DF>(src, b + t.z * sp + t.y * sr + t.x);
+    }
+#pragma unroll
+    for (int k = 0; k < kPerThread3; ++k) {
+        const TilePos t = tile_pos(k);
+        if (t.z < bz && t.y < by && t.x < bx) sm[t.i] = r[k];
+    }
+}
+
+template <class S, bool DF>
+__device__ __forceinline__ void lds_drain(const df* sm, void* dst, int64_t b, int64_t sp, int64_t sr, int bz,
+                                          int by, int bx) {
+#pragma unroll
+    for (int k = 0; k < kPerThread3; ++k) {
+        const TilePos t = tile_pos(k);
+        if (t.z < bz && t.y < by && t.x < bx) st_val<S, DF>(dst, b + t.z * sp + t.y * sr + t.x, sm[t.i]);
+    }
+}
+
+template <class S, bool SRCDF, bool LLDF>
+__device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, df* sm) {
+    const Counts3 c = tile_counts(p, oz, oy, ox);
+    lds_fill<S, SRCDF>(sm, p.src, item * p.src_b + oz * p.src_p + oy * p.src_r + ox, p.src_p, p.src_r, c.z,
+                       c.y, c.x);
+    __syncthreads();
+    for (int j = 1; j <= p.levels; ++j) {
+        const int nz = c.cz(j - 1), ny = c.cy(j - 1), nx = c.cx(j - 1);
+        lds_level<0, false>(sm, nz, ny, nx);
+        lds_level<1, false>(sm, nz, ny, nx);
+        lds_level<2, false>(sm, nz, ny, nx);
+        lds_details<S, false>(p, item, oz, oy, ox, c, j, sm);
+    }
+    const int J = p.levels;
+    lds_drain<S, LLDF>(sm, p.ll, item * p.ll_b + (oz >> J) * p.ll_p + (oy >> J) * p.ll_r + (ox >> J), p.ll_p,
+                       p.ll_r, c.cz(J), c.cy(J), c.cx(J));
+}
+
+template <class S, bool DSTDF, bool LLDF>
+__device__ void inv3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, df* sm) {
+    const Counts3 c = tile_counts(p, oz, oy, ox);
+    const int J = p.levels;
+    lds_fill<S, LLDF>(sm, p.ll, item * p.ll_b + (oz >> J) * p.ll_p + (oy >> J) * p.ll_r + (ox >> J), p.ll_p,
+                      p.ll_r, c.cz(J), c.cy(J), c.cx(J));
+    for (int j = J; j >= 1; --j) {
+        lds_details<S, true>(p, item, oz, oy, ox, c, j, sm);
+        __syncthreads();
+        const int nz = c.cz(j - 1), ny = c.cy(j - 1), nx = c.cx(j - 1);
+        lds_level<2, true>(sm, nz, ny, nx);
+        lds_level<1, true>(sm, nz, ny, nx);
+        lds_level<0, true>(sm, nz, ny, nx);
+    }
+    lds_drain<S, DSTDF>(sm, p.dst, item * p.dst_b + oz * p.dst_p + oy * p.dst_r + ox, p.dst_p, p.dst_r, c.z,
+                        c.y, c.x);
+}
+
+// ---------------------------------------------------------------------------
+// Register path for interior tiles.
+//
+// Thread map (256 threads, 4 wavefronts): tx = lane & 15 owns the RX
+// samples x in [RX tx, RX tx + RX) (RX = 16 bytes of storage: 4 FP32 or 8
+// BF16/FP16 samples, so an interior tile is 16 RX wide); ty = lane bit 4 |
+// wave bit 0 << 1 owns rows 2 ty, 2 ty + 1; tz = lane bit 5 | wave bit 1 << 1
+// owns planes 2 tz, 2 tz + 1.  Each load instruction reads four 16-lane row
+// segments of 16 RX samples, and each level-1 band store writes four rows of
+// 8 RX bytes (128 B in both formats).  A thread's RX/2 blocks of 2 x 2 x 2
+// give level 1; the level-2 partners along y and z are lanes ^ 16 and ^ 32
+// of the same wavefront; level 3 combines the four wavefronts through LDS.
+// ---------------------------------------------------------------------------
+struct Map3 {
+    int lane, wv, tx, ty, tz;
+    bool yo, zo;                               // odd level-1 row / plane of a level-2 pair
+};
+
+__device__ __forceinline__ Map3 map3() {
+    Map3 m;
+    m.lane = threadIdx.x & 63;
+    m.wv = threadIdx.x >> 6;
+    m.tx = m.lane & 15;
+    m.ty = ((m.lane >> 4) & 1) | ((m.wv & 1) << 1);
+    m.tz = ((m.lane >> 5) & 1) | ((m.wv >> 1) << 1);
+    m.yo = (m.lane >> 4) & 1;
+    m.zo = (m.lane >> 5) & 1;
+    return m;
+}
+
+template <class S, bool RDF>
+struct Rx3 {
+    // samples per thread along x: 16 bytes of storage, or 4 pairs when the
+    // region is pair scratch (a deep pass)
+    static constexpr int RX = RDF ? 4 : 16 / S::kBytes;
+    static constexpr int NB = RX / 2;          // level-1 blocks per thread
+    static constexpr int NP = NB / 2;          // level-2 blocks per thread (along x)
+    static constexpr int TX = 16 * RX;         // interior tile width
+    static constexpr int X2 = 16 * NP;         // LLL_2 width of a tile
+};
+
+template <class S, bool RDF, int LV, bool LLDF>
+__device__ void fwd3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, df* sm) {
+    using raw = typename S::raw;
+    using R = Rx3<S, RDF>;
+    constexpr int RX = R::RX, NB = R::NB, NP = R::NP;
+    const Map3 m = map3();
+    const int64_t sb = item * p.src_b + (oz + 2 * m.tz) * p.src_p + (oy + 2 * m.ty) * p.src_r + ox + RX * m.tx;
+    raw* det = reinterpret_cast<raw*>(p.det) + item * p.det_b;
+
+    // level 1: NB blocks per thread; from storage the details are formed in
+    // FP32 and LLL as a pair, from pair scratch everything in pairs
+    const Level3 L1 = level_sizes(p, 1);
+    df lll[NB];
+    float d1[8][NB];
+    if constexpr (RDF) {
+        const df* src = reinterpret_cast<const df*>(p.src) + sb;
+        df v[2][2][RX];
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int e = 0; e < RX; ++e) v[dz][dy][e] = src[dz * p.src_p + dy * p.src_r + e];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            df q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[i] = v[i >> 2][(i >> 1) & 1][2 * b + (i & 1)];
+            bfly8_df<false>(q);
+            lll[b] = df_c3(q[0]);
+#pragma unroll
+            for (int i = 1; i < 8; ++i) d1[i][b] = df_round(df_c3(q[i]));
+        }
+    } else {
+        const raw* src = reinterpret_cast<const raw*>(p.src) + sb;
+        float v[2][2][RX];
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) ld_vec<S, RX>(src + dz * p.src_p + dy * p.src_r, v[dz][dy]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[i] = v[i >> 2][(i >> 1) & 1][2 * b + (i & 1)];
+            lll[b] = df_c3(df_add(df_sum4f(q[0], q[1], q[2], q[3]), df_sum4f(q[4], q[5], q[6], q[7])));
+            bfly8<false>(q);
+#pragma unroll
+            for (int i = 1; i < 8; ++i) d1[i][b] = q[i] * kC3Hi;
+        }
+    }
+#pragma unroll
+    for (int c = 1; c < 8; ++c) {
+        const int64_t gz = ((c >> 2) ? L1.D : 0) + (oz >> 1) + m.tz;
+        const int64_t gy = (((c >> 1) & 1) ? L1.H : 0) + (oy >> 1) + m.ty;
+        const int64_t gx = ((c & 1) ? L1.W : 0) + (ox >> 1) + NB * m.tx;
+        st_vec<S, NB>(det + gz * p.det_p + gy * p.det_r + gx, d1[c]);
+    }
+    if constexpr (LV == 1) {
+        const int64_t g = item * p.ll_b + ((oz >> 1) + m.tz) * p.ll_p + ((oy >> 1) + m.ty) * p.ll_r +
+                          (ox >> 1) + NB * m.tx;
+        if constexpr (LLDF) {
+            df* ll = reinterpret_cast<df*>(p.ll);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ll[g + b] = lll[b];
+        } else {
+            float o[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) o[b] = df_round(lll[b]);
+            st_vec<S, NB>(reinterpret_cast<raw*>(p.ll) + g, o);
+        }
+        return;
+    }
+
+    // level 2: x in the thread, y with lane ^ 16, z with lane ^ 32
+    df s[NP], t[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        s[q] = df_add(lll[2 * q], lll[2 * q + 1]);
+        t[q] = df_sub(lll[2 * q + 1], lll[2 * q]);
+        const df ps = shfl_xor_pair(s[q], 16), pt = shfl_xor_pair(t[q], 16);
+        s[q] = m.yo ? df_sub(s[q], ps) : df_add(s[q], ps);
+        t[q] = m.yo ? df_sub(t[q], pt) : df_add(t[q], pt);
+        const df zs = shfl_xor_pair(s[q], 32), zt = shfl_xor_pair(t[q], 32);
+        s[q] = df_c3(m.zo ? df_sub(s[q], zs) : df_add(s[q], zs));    // code (L, yo, zo)
+        t[q] = df_c3(m.zo ? df_sub(t[q], zt) : df_add(t[q], zt));    // code (H, yo, zo)
+    }
+    const Level3 L2 = level_sizes(p, 2);
+    const int y2 = m.ty >> 1, z2 = m.tz >> 1;
+    const bool low = !m.yo && !m.zo;           // lanes holding LLL_2
+    {
+        const int64_t gz = (m.zo ? L2.D : 0) + (oz >> 2) + z2;
+        const int64_t gy = (m.yo ? L2.H : 0) + (oy >> 2) + y2;
+        raw* row = det + gz * p.det_p + gy * p.det_r + (ox >> 2) + NP * m.tx;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            st1_cached<S>(row + L2.W + q, df_round(t[q]));
+            if (!low) st1_cached<S>(row + q, df_round(s[q]));
+        }
+    }
+    if constexpr (LV == 2) {
+        if (low) {
+            const int64_t g = item * p.ll_b + ((oz >> 2) + z2) * p.ll_p + ((oy >> 2) + y2) * p.ll_r +
+                              (ox >> 2) + NP * m.tx;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) st_val<S, LLDF>(p.ll, g + q, s[q]);
+        }
+        return;
+    }
+
+    // level 3: LLL_2 of the tile (2 x 2 x X2) through LDS; 4 NP threads of
+    // wavefront 0 each take one 2 x 2 x 2 block
+    constexpr int X2 = R::X2;
+    if (low) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) sm[(z2 * 2 + y2) * X2 + NP * m.tx + q] = s[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < X2 / 2) {
+        const int k = threadIdx.x;
+        df q[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) q[i] = sm[((i >> 2) * 2 + ((i >> 1) & 1)) * X2 + 2 * k + (i & 1)];
+        bfly8_df<false>(q);
+        const Level3 L3 = level_sizes(p, 3);
+#pragma unroll
+        for (int c = 1; c < 8; ++c) {
+            const int64_t gz = ((c >> 2) ? L3.D : 0) + (oz >> 3);
+            const int64_t gy = (((c >> 1) & 1) ? L3.H : 0) + (oy >> 3);
+            const int64_t gx = ((c & 1) ? L3.W : 0) + (ox >> 3) + k;
+            st1_cached<S>(det + gz * p.det_p + gy * p.det_r + gx, df_round(df_c3(q[c])));
+        }
+        st_val<S, LLDF>(p.ll, item * p.ll_b + (oz >> 3) * p.ll_p + (oy >> 3) * p.ll_r + (ox >> 3) + k,
+                        df_c3(q[0]));
+    }
+}
+
+template <class S, bool RDF, int LV, bool LLDF>
+__device__ void inv3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, df* sm) {
+    using raw = typename S::raw;
+    using R = Rx3<S, RDF>;
+    constexpr int RX = R::RX, NB = R::NB, NP = R::NP, X2 = R::X2;
+    const Map3 m = map3();
+    const raw* det = reinterpret_cast<const raw*>(p.det) + item * p.det_b;
+    df lll[NB];
+    if constexpr (LV == 1) {
+        const int64_t g = item * p.ll_b + ((oz >> 1) + m.tz) * p.ll_p + ((oy >> 1) + m.ty) * p.ll_r +
+                          (ox >> 1) + NB * m.tx;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) lll[b] = ld_val<S, LLDF>(p.ll, g + b);
+    } else {
+        const int y2 = m.ty >> 1, z2 = m.tz >> 1;
+        const bool low = !m.yo && !m.zo;
+        if constexpr (LV == 3) {
+            if (threadIdx.x < X2 / 2) {
+                const int k = threadIdx.x;
+                const Level3 L3 = level_sizes(p, 3);
+                df q[8];
+                q[0] = ld_val<S, LLDF>(p.ll, item * p.ll_b + (oz >> 3) * p.ll_p + (oy >> 3) * p.ll_r +
+                                                 (ox >> 3) + k);
+#pragma unroll
+                for (int c = 1; c < 8; ++c) {
+                    const int64_t gz = ((c >> 2) ? L3.D : 0) + (oz >> 3);
+                    const int64_t gy = (((c >> 1) & 1) ? L3.H : 0) + (oy >> 3);
+                    const int64_t gx = ((c & 1) ? L3.W : 0) + (ox >> 3) + k;
+                    q[c] = df_from(ld1<S>(det + gz * p.det_p + gy * p.det_r + gx));
+                }
+                bfly8_df<true>(q);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    sm[((i >> 2) * 2 + ((i >> 1) & 1)) * X2 + 2 * k + (i & 1)] = df_c3(q[i]);
+            }
+            __syncthreads();
+        }
+        const Level3 L2 = level_sizes(p, 2);
+        const int64_t gz = (m.zo ? L2.D : 0) + (oz >> 2) + z2;
+        const int64_t gy = (m.yo ? L2.H : 0) + (oy >> 2) + y2;
+        const raw* row = det + gz * p.det_p + gy * p.det_r + (ox >> 2) + NP * m.tx;
+        const int64_t gl = item * p.ll_b + ((oz >> 2) + z2) * p.ll_p + ((oy >> 2) + y2) * p.ll_r +
+                           (ox >> 2) + NP * m.tx;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            df t = df_from(ld1<S>(row + L2.W + q));
+            df s;
+            if (!low) {
+                s = df_from(ld1<S>(row + q));
+            } else if constexpr (LV == 3) {
+                s = sm[(z2 * 2 + y2) * X2 + NP * m.tx + q];
+            } else {
+                s = ld_val<S, LLDF>(p.ll, gl + q);
+            }
+            // undo z (lane ^ 32), then y (lane ^ 16): even member a - d, odd a + d
+            const df zs = shfl_xor_pair(s, 32), zt = shfl_xor_pair(t, 32);
+            s = m.zo ? df_add(zs, s) : df_sub(s, zs);
+            t = m.zo ? df_add(zt, t) : df_sub(t, zt);
+            const df ys = shfl_xor_pair(s, 16), yt = shfl_xor_pair(t, 16);
+            s = m.yo ? df_add(ys, s) : df_sub(s, ys);
+            t = m.yo ? df_add(yt, t) : df_sub(t, yt);
+            lll[2 * q] = df_c3(df_sub(s, t));
+            lll[2 * q + 1] = df_c3(df_add(s, t));
+        }
+    }
+
+    // level 1: LLL_1 and the seven detail octants of the NB blocks, in FP32
+    // into storage, in pairs into pair scratch
+    const Level3 L1 = level_sizes(p, 1);
+    float d1[8][NB];
+#pragma unroll
+    for (int c = 1; c < 8; ++c) {
+        const int64_t gz = ((c >> 2) ? L1.D : 0) + (oz >> 1) + m.tz;
+        const int64_t gy = (((c >> 1) & 1) ? L1.H : 0) + (oy >> 1) + m.ty;
+        const int64_t gx = ((c & 1) ? L1.W : 0) + (ox >> 1) + NB * m.tx;
+        ld_vec<S, NB>(det + gz * p.det_p + gy * p.det_r + gx, d1[c]);
+    }
+    const int64_t db = item * p.dst_b + (oz + 2 * m.tz) * p.dst_p + (oy + 2 * m.ty) * p.dst_r + ox + RX * m.tx;
+    if constexpr (RDF) {
+        df* dst = reinterpret_cast<df*>(p.dst) + db;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            df q[8];
+            q[0] = lll[b];
+#pragma unroll
+            for (int i = 1; i < 8; ++i) q[i] = df_from(d1[i][b]);
+            bfly8_df<true>(q);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                dst[(i >> 2) * p.dst_p + ((i >> 1) & 1) * p.dst_r + 2 * b + (i & 1)] = df_c3(q[i]);
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) d1[0][b] = df_round(lll[b]);
+        float v[2][2][RX];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[i] = d1[i][b];
+            bfly8<true>(q);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i >> 2][(i >> 1) & 1][2 * b + (i & 1)] = q[i] * kC3Hi;
+        }
+        raw* dst = reinterpret_cast<raw*>(p.dst) + db;
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) st_vec<S, RX>(dst + dz * p.dst_p + dy * p.dst_r, v[dz][dy]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.  Interior tiles (the register path) and the other tiles (the LDS
+// path) are separate launches, so that each keeps its own register budget.
+// Tiles run x-fastest; a grid-stride loop covers grids beyond the cap.
+// RDF: the region (analysis source / synthesis destination) is pair
+// scratch; LDF: the pass's deepest LLL is pair scratch.
+// ---------------------------------------------------------------------------
+template <class S, bool RDF>
+__device__ __forceinline__ void full_origin(const Pass3D& p, int64_t t, int64_t& item, int64_t& oz,
+                                            int64_t& oy, int64_t& ox) {
+    ox = (t % p.fx) * Rx3<S, RDF>::TX;
+    t /= p.fx;
+    oy = (t % p.fy) * kTY;
+    t /= p.fy;
+    oz = (t % p.fz) * kTZ;
+    item = t / p.fz;
+}
+
+// Edge tile e of an item (generic tiles, 64 wide): the slab tz >= fz, then
+// ty >= fy (tz < fz), then the columns from x = cx0 on (tz < fz, ty < fy),
+// where the interior tiles (fx of them, possibly wider) end.
+__device__ __forceinline__ void edge_origin(const Pass3D& p, int64_t e, int64_t& item, int64_t& oz,
+                                            int64_t& oy, int64_t& ox) {
+    const int64_t a = (p.ntz - p.fz) * p.nty * p.ntx;
+    const int64_t b = p.fz * (p.nty - p.fy) * p.ntx;
+    const int64_t c = p.fz * p.fy * p.ncx;
+    const int64_t per = a + b + c;
+    item = e / per;
+    e -= item * per;
+    int64_t tz, ty, tx;
+    if (e < a) {
+        tx = e % p.ntx;
+        ty = (e / p.ntx) % p.nty;
+        tz = p.fz + e / (p.ntx * p.nty);
+    } else if (e < a + b) {
+        e -= a;
+        tx = e % p.ntx;
+        ty = p.fy + (e / p.ntx) % (p.nty - p.fy);
+        tz = e / (p.ntx * (p.nty - p.fy));
+    } else {
+        e -= a + b;
+        oz = (e / (p.ncx * p.fy)) * kTZ;
+        oy = ((e / p.ncx) % p.fy) * kTY;
+        ox = p.cx0 + (e % p.ncx) * kTX;
+        return;
+    }
+    oz = tz * kTZ;
+    oy = ty * kTY;
+    ox = tx * kTX;
+}
+
+template <class S, bool RDF, int LV, bool LDF>
+__global__ __launch_bounds__(kThreads3) void fwd3d_full_kernel(Pass3D p) {
+    __shared__ df sm[4 * Rx3<S, RDF>::X2];
+    for (int64_t t = blockIdx.x; t < p.nfull; t += gridDim.x) {
+        int64_t item, oz, oy, ox;
+        full_origin<S, RDF>(p, t, item, oz, oy, ox);
+        fwd3d_regs<S, RDF, LV, LDF>(p, item, oz, oy, ox, sm);
+        if (LV == 3) __syncthreads();
+    }
+}
+
+template <class S, bool RDF, int LV, bool LDF>
+__global__ __launch_bounds__(kThreads3) void inv3d_full_kernel(Pass3D p) {
+    __shared__ df sm[4 * Rx3<S, RDF>::X2];
+    for (int64_t t = blockIdx.x; t < p.nfull; t += gridDim.x) {
+        int64_t item, oz, oy, ox;
+        full_origin<S, RDF>(p, t, item, oz, oy, ox);
+        inv3d_regs<S, RDF, LV, LDF>(p, item, oz, oy, ox, sm);
+        if (LV == 3) __syncthreads();
+    }
+}
+
+template <class S, bool RDF, bool LDF>
+__global__ __launch_bounds__(kThreads3) void fwd3d_edge_kernel(Pass3D p) {
+    __shared__ df sm[kTile];
+    for (int64_t t = blockIdx.x; t < p.nedge; t += gridDim.x) {
+        int64_t item, oz, oy, ox;
+        edge_origin(p, t, item, oz, oy, ox);
+        fwd3d_lds<S, RDF, LDF>(p, item, oz, oy, ox, sm);
+        __syncthreads();
+    }
+}
+
+template <class S, bool RDF, bool LDF>
+__global__ __launch_bounds__(kThreads3) void inv3d_edge_kernel(Pass3D p) {
+    __shared__ df sm[kTile];
+    for (int64_t t = blockIdx.x; t < p.nedge; t += gridDim.x) {
+        int64_t item, oz, oy, ox;
+        edge_origin(p, t, item, oz, oy, ox);
+        inv3d_lds<S, RDF, LDF>(p, item, oz, oy, ox, sm);
+        __syncthreads();
+    }
+}
+
+constexpr int64_t kGridCap3 = (int64_t)1 << 22;
+
+inline unsigned grid3(int64_t n) { return (unsigned)(n < kGridCap3 ? n : kGridCap3); }
+
+template <class S, bool RDF, bool LDF>
+void launch3_full(const Pass3D& p, bool inverse, hipStream_t s) {
+    const dim3 g(grid3(p.nfull)), b(kThreads3);
+    if (inverse) {
+        if (p.levels == 3) hipLaunchKernelGGL((inv3d_full_kernel<S, RDF, 3, LDF>), g, b, 0, s, p);
+        else if (p.levels == 2) hipLaunchKernelGGL((inv3d_full_kernel<S, RDF, 2, LDF>), g, b, 0, s, p);
+        else hipLaunchKernelGGL((inv3d_full_kernel<S, RDF, 1, LDF>), g, b, 0, s, p);
+    } else {
+        if (p.levels == 3) hipLaunchKernelGGL((fwd3d_full_kernel<S, RDF, 3, LDF>), g, b, 0, s, p);
+        else if (p.levels == 2) hipLaunchKernelGGL((fwd3d_full_kernel<S, RDF, 2, LDF>), g, b, 0, s, p);
+        else hipLaunchKernelGGL((fwd3d_full_kernel<S, RDF, 1, LDF>), g, b, 0, s, p);
+    }
+}
+
+template <class S, bool RDF, bool LDF>
+void launch3_edge(const Pass3D& p, bool inverse, hipStream_t s) {
+    const dim3 g(grid3(p.nedge)), b(kThreads3);
+    if (inverse) hipLaunchKernelGGL((inv3d_edge_kernel<S, RDF, LDF>), g, b, 0, s, p);
+    else hipLaunchKernelGGL((fwd3d_edge_kernel<S, RDF, LDF>), g, b, 0, s, p);
+}
+
+template <class S>
+hipError_t launch3_s(const Pass3D& p, bool inverse, bool rdf, bool ldf, hipStream_t s) {
+    if (p.nfull > 0) {
+        if (rdf) {
+            if (ldf) launch3_full<S, true, true>(p, inverse, s);
+            else launch3_full<S, true, false>(p, inverse, s);
+        } else {
+            if (ldf) launch3_full<S, false, true>(p, inverse, s);
+            else launch3_full<S, false, false>(p, inverse, s);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (p.nedge > 0) {
+        if (rdf) {
+            if (ldf) launch3_edge<S, true, true>(p, inverse, s);
+            else launch3_edge<S, true, false>(p, inverse, s);
+        } else {
+            if (ldf) launch3_edge<S, false, true>(p, inverse, s);
+            else launch3_edge<S, false, false>(p, inverse, s);
+        }
+    }
+    return hipGetLastError();
+}
+
+struct Region3D {
+    int64_t d, h, w;
+    int levels;
+};
+
+}  // namespace
+
+int run_3d(const void* in, void* out, int64_t D, int64_t H, int64_t W, int L, int64_t batch, int dtype,
+           bool inverse, hipStream_t s) {
+    std::vector<Region3D> ps;
+    {
+        int64_t d = D, h = H, w = W;
+        for (int left = L; left > 0;) {
+            const int lp = left < kMaxPassLevels3D ? left : kMaxPassLevels3D;
+            ps.push_back({d, h, w, lp});
+            d = ceil_shift_host(d, lp);
+            h = ceil_shift_host(h, lp);
+            w = ceil_shift_host(w, lp);
+            left -= lp;
+        }
+    }
+    const int np = (int)ps.size();
+    // pair scratch between passes: two ping-pong buffers sized for the
+    // region after the first pass
+    void* scratch = nullptr;
+    int64_t half = 0;
+    if (np > 1) {
+        half = batch * ps[1].d * ps[1].h * ps[1].w;
+        hipError_t e = hipMallocAsync(&scratch, (size_t)(2 * half * (int64_t)sizeof(float) * 2), s);
+        if (e != hipSuccess) return hip_error(e, "hipMallocAsync (3D pass scratch)");
+    }
+    auto buf = [&](int k) -> void* { return (char*)scratch + ((k & 1) ? 0 : half) * 8; };
+
+    int rc = HAAR_OK;
+    for (int step = 0; step < np && rc == HAAR_OK; ++step) {
+        const int k = inverse ? np - 1 - step : step;
+        const Region3D& r = ps[k];
+        const bool rdf = k > 0, ldf = k < np - 1;
+        Pass3D p{};
+        p.d = r.d;
+        p.h = r.h;
+        p.w = r.w;
+        p.batch = batch;
+        p.levels = r.levels;
+        p.det = const_cast<void*>(inverse ? in : (const void*)out);
+        p.det_p = H * W;
+        p.det_r = W;
+        p.det_b = D * H * W;
+        void* rptr = k == 0 ? (void*)(inverse ? out : in) : buf(k);
+        const int64_t rp = k == 0 ? H * W : r.h * r.w, rr = k == 0 ? W : r.w;
+        const int64_t rb = k == 0 ? D * H * W : r.d * r.h * r.w;
+        const int64_t nd = ceil_shift_host(r.d, r.levels), nh = ceil_shift_host(r.h, r.levels);
+        const int64_t nw = ceil_shift_host(r.w, r.levels);
+        p.ll = k == np - 1 ? (void*)(inverse ? in : out) : buf(k + 1);
+        p.ll_p = k == np - 1 ? H * W : nh * nw;
+        p.ll_r = k == np - 1 ? W : nw;
+        p.ll_b = k == np - 1 ? D * H * W : nd * nh * nw;
+        if (inverse) {
+            p.dst = rptr; p.dst_p = rp; p.dst_r = rr; p.dst_b = rb;
+        } else {
+            p.src = rptr; p.src_p = rp; p.src_r = rr; p.src_b = rb;
+        }
+        p.ntz = ceil_shift_host(r.d, 3);
+        p.nty = ceil_shift_host(r.h, 3);
+        p.ntx = ceil_shift_host(r.w, 6);
+        // interior tile width: 16 threads of 16 bytes of storage, or of 4
+        // pairs when the region is pair scratch
+        const int ftx = 16 * (rdf ? 4 : 16 / elem_bytes(dtype));
+        p.fz = r.d / kTZ;
+        p.fy = r.h / kTY;
+        p.fx = r.w / ftx;
+        p.cx0 = p.fx * ftx;
+        p.ncx = (r.w - p.cx0 + kTX - 1) / kTX;
+        p.nfull = p.fz * p.fy * p.fx * batch;
+        p.nedge = ((p.ntz - p.fz) * p.nty * p.ntx + p.fz * (p.nty - p.fy) * p.ntx + p.fz * p.fy * p.ncx) * batch;
+        hipError_t e;
+        if (dtype == HAAR_F32) e = launch3_s<StF32>(p, inverse, rdf, ldf, s);
+        else if (dtype == HAAR_BF16) e = launch3_s<StBF16>(p, inverse, rdf, ldf, s);
+        else e = launch3_s<StF16>(p, inverse, rdf, ldf, s);
+        if (e != hipSuccess) rc = hip_error(e, inverse ? "inv3d launch" : "fwd3d launch");
+    }
+    if (scratch) {
+        hipError_t e = hipFreeAsync(scratch, s);
+        if (e != hipSuccess && rc == HAAR_OK) rc = hip_error(e, "hipFreeAsync");
+    }
+    return rc;
+}
+
+}  // namespace haar

@@ -395,6 +395,40 @@ int haar_inv_2d(const void* y, void* x, int64_t height, int64_t width, int32_t l
     return api_2d(y, x, height, width, levels, batch, dtype, stream, true);
 }
 
+int haar_max_levels_3d(int64_t depth, int64_t height, int64_t width) {
+    if (depth < 1 || height < 1 || width < 1) return -1;
+    int64_t m = depth > height ? depth : height;
+    m = m > width ? m : width;
+    return max_levels(m);
+}
+
+static int api_3d(const void* in, void* out, int64_t depth, int64_t height, int64_t width,
+                  int32_t levels, int64_t batch, int32_t dtype, void* stream, bool inverse) {
+    if (depth < 1 || height < 1 || width < 1)
+        return set_error(HAAR_ERR_SHAPE, "depth %lld / height %lld / width %lld < 1", (long long)depth,
+                         (long long)height, (long long)width);
+    if (height > INT64_MAX / width || depth > INT64_MAX / (height * width))
+        return set_error(HAAR_ERR_SHAPE, "depth * height * width overflows");
+    bool nothing = false;
+    int rc = check_common(in, out, depth * height * width, levels,
+                          haar_max_levels_3d(depth, height, width), batch, dtype, &nothing);
+    if (rc != HAAR_OK || nothing) return rc;
+    if (rc = fault_injected(); rc != HAAR_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (levels == 0) return copy_levels0(in, out, depth * height * width * batch * elem_bytes(dtype), s);
+    return run_3d(in, out, depth, height, width, levels, batch, dtype, inverse, s);
+}
+
+int haar_fwd_3d(const void* x, void* y, int64_t depth, int64_t height, int64_t width, int32_t levels,
+                int64_t batch, int32_t dtype, void* stream) {
+    return api_3d(x, y, depth, height, width, levels, batch, dtype, stream, false);
+}
+
+int haar_inv_3d(const void* y, void* x, int64_t depth, int64_t height, int64_t width, int32_t levels,
+                int64_t batch, int32_t dtype, void* stream) {
+    return api_3d(y, x, depth, height, width, levels, batch, dtype, stream, true);
+}
+
 // Fused shrinkage: the plain-call checks, then mode and thresholds (host
 // array, read during the call), then the fused depth.
 static int check_shrink(int32_t levels, int32_t mode, const float* thresholds, int max_fused) {

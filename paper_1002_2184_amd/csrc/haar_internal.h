@@ -33,6 +33,10 @@ int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch
 int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype, bool inverse,
            hipStream_t s, int cfg_override);
 
+// Separable 3D on [batch][D][H][W]: passes of up to 3 fused levels.
+int run_3d(const void* in, void* out, int64_t D, int64_t H, int64_t W, int L, int64_t batch, int dtype,
+           bool inverse, hipStream_t s);
+
 // Fused shrinkage (analysis, thresholding of the details, synthesis): one
 // chunk of kShrinkChunk samples (1D, levels <= 12) or one 32-row tile (2D,
 // levels <= 5) per work-group.

@@ -96,6 +96,29 @@ def inv2d(y: torch.Tensor, levels: int, out: torch.Tensor | None = None) -> torc
     return x
 
 
+def fwd3d(x: torch.Tensor, levels: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Multi-level separable 3D analysis on the last three axes (depth,
+    height, width): x, then y, then z per level, recursion on LLL."""
+    x = _prep(x, 3)
+    y = _out(x, out)
+    d, h, w = x.shape[-3], x.shape[-2], x.shape[-1]
+    batch = x.numel() // (d * h * w) if d * h * w > 0 else 0
+    _abi.check(_abi.haar_fwd_3d(x.data_ptr(), y.data_ptr(), d, h, w, int(levels), batch, dtype_code(x),
+                                _stream(x.device)))
+    return y
+
+
+def inv3d(y: torch.Tensor, levels: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Multi-level separable 3D synthesis on the last three axes (inverse of fwd3d)."""
+    y = _prep(y, 3)
+    x = _out(y, out)
+    d, h, w = y.shape[-3], y.shape[-2], y.shape[-1]
+    batch = y.numel() // (d * h * w) if d * h * w > 0 else 0
+    _abi.check(_abi.haar_inv_3d(y.data_ptr(), x.data_ptr(), d, h, w, int(levels), batch, dtype_code(y),
+                                _stream(y.device)))
+    return x
+
+
 SHRINK_MODES = {"hard": 0, "soft": 1}
 
 

@@ -50,6 +50,10 @@ def test_max_levels(abi):
     assert abi.haar_max_levels_2d(4096, 4096) == 12
     assert abi.haar_max_levels_2d(3, 1000) == 10
     assert abi.haar_max_levels_2d(0, 5) == -1
+    assert abi.haar_max_levels_3d(256, 256, 256) == 8
+    assert abi.haar_max_levels_3d(3, 1000, 5) == 10
+    assert abi.haar_max_levels_3d(1, 1, 1) == 0
+    assert abi.haar_max_levels_3d(4, 0, 4) == -1
 
 
 X, Y = 0x10000000, 0x20000000     # fake, non-overlapping device addresses (never dereferenced)
@@ -82,6 +86,12 @@ X, Y = 0x10000000, 0x20000000     # fake, non-overlapping device addresses (neve
     (lambda a: a.haar_direct_1d(X, Y, 64, 3, 1, 0, 0, 0x30000000, 16, 0), 6),      # too small
     (lambda a: a.haar_direct_1d(X, Y, 64, 3, 1, 0, 0, 0x30000002, 1 << 20, 0), 6), # misaligned
     (lambda a: a.haar_direct_1d(X, Y, 64, 7, 1, 0, 0, 0x30000000, 1 << 20, 0), 4),  # levels
+    (lambda a: a.haar_fwd_3d(X, Y, 0, 8, 8, 1, 1, 0, 0), 3),                        # depth < 1
+    (lambda a: a.haar_fwd_3d(X, Y, 8, 8, 8, 4, 1, 0, 0), 4),                        # levels > log2
+    (lambda a: a.haar_inv_3d(X, Y, 8, 8, 8, 1, 1, 3, 0), 2),                        # dtype
+    (lambda a: a.haar_inv_3d(X, X + 64, 8, 8, 8, 1, 1, 0, 0), 5),                   # overlap
+    (lambda a: a.haar_fwd_3d(X, Y, 1 << 30, 1 << 30, 1 << 30, 1, 1, 0, 0), 3),      # size overflow
+    (lambda a: a.haar_fwd_3d(0, Y, 8, 8, 8, 1, 1, 0, 0), 1),                        # NULL input
 ])
 def test_validation_codes(abi, call, code):
     assert call(abi) == code
@@ -115,6 +125,7 @@ def test_batch_zero_is_a_noop(abi):
     assert abi.haar_shrink_1d(0, 0, 16, 2, 0, 0, 0, [1.0, 1.0], 0) == 0
     assert abi.haar_fwd_1d(0, 0, 16, 2, 0, 0, 0) == 0
     assert abi.haar_inv_2d(0, 0, 8, 8, 3, 0, 1, 0) == 0
+    assert abi.haar_fwd_3d(0, 0, 8, 8, 8, 3, 0, 2, 0) == 0
 
 
 def test_fault_injection_maps_to_hip_error(abi, monkeypatch):

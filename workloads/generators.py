@@ -9,7 +9,9 @@ available here, so every workload is synthetic:
   1 kHz plus N(0, 0.1^2) noise (biosignal stand-in);
 * ``smooth_image``     -- a sum of 8 random 2D sinusoids of amplitude 100 plus
   0.1 * U[0, 255] noise (natural-image stand-in);
-* ``uniform_images``   -- U[0, 1] images of uneven even sizes.
+* ``uniform_images``   -- U[0, 1] images of uneven even sizes;
+* ``phantom_volume``   -- CT-like volumes (ellipsoids of tissue intensity in
+  air, plus noise) for the 3D transform.
 
 All draws use ``numpy.random.default_rng(SEED + config)`` (PCG64) in float64
 and are rounded to the storage type with round-to-nearest-even.  Reduced
@@ -121,6 +123,32 @@ def smooth_image(rng: np.random.Generator, h: int, w: int, terms: int = 8,
         img += amplitude * (np.outer(np.cos(cy), np.sin(cx)) + np.outer(np.sin(cy), np.cos(cx)))
     img += 0.1 * rng.uniform(0.0, 255.0, (h, w))
     return img
+
+
+def phantom_volume(rng: np.random.Generator, d: int, h: int, w: int, organs: int = 8) -> np.ndarray:
+    """A CT-like volume [d, h, w] (float64): air 0, a body ellipsoid of 1.0
+    (radii 0.45 of each side, centred), `organs` ellipsoids inside it with
+    radii U[0.04, 0.18] of each side and intensities U[-0.5, 0.8] added,
+    plus N(0, 0.02^2) noise.  Stand-in for the medical volumes of the
+    paper's application; the intensities mimic normalised Hounsfield units."""
+    zs = (np.arange(d, dtype=np.float64) + 0.5) / d
+    ys = (np.arange(h, dtype=np.float64) + 0.5) / h
+    xs = (np.arange(w, dtype=np.float64) + 0.5) / w
+
+    def ellipsoid(c, r):
+        qz = ((zs - c[0]) / r[0]) ** 2
+        qy = ((ys - c[1]) / r[1]) ** 2
+        qx = ((xs - c[2]) / r[2]) ** 2
+        return (qz[:, None, None] + qy[None, :, None] + qx[None, None, :]) < 1.0
+
+    v = np.zeros((d, h, w), dtype=np.float64)
+    v[ellipsoid((0.5, 0.5, 0.5), (0.45, 0.45, 0.45))] = 1.0
+    for _ in range(organs):
+        c = rng.uniform(0.3, 0.7, 3)
+        r = rng.uniform(0.04, 0.18, 3)
+        v[ellipsoid(c, r)] += rng.uniform(-0.5, 0.8)
+    v += rng.normal(0.0, 0.02, (d, h, w))
+    return v
 
 
 def uneven_even_sizes(rng: np.random.Generator, count: int, lo: int = 128,
