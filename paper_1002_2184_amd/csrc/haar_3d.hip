@@ -12,12 +12,20 @@
 // whose bit is set.
 //
 // One work-group owns a tile of 8 x 8 x 64 samples (z, y, x; interior
-// tiles of 16-bit data are 128 wide), so a pass fuses three levels.  Interior tiles of a storage-typed region run the
-// register path: level 1 inside each thread (2 x 2 x 2 blocks), level 2
-// across lanes with shuffles, level 3 on one wavefront through LDS.  Edge
-// tiles, odd counts and the passes that start from scratch run a generic
-// path that keeps the tile in LDS as compensated pairs.  Deeper transforms
-// chain passes through compensated FP32 scratch.
+// tiles of 16-bit data are 128 wide), so a pass fuses three levels.
+// Interior tiles run a register path: level 1 inside each thread
+// (2 x 2 x 2 blocks), level 2 across lanes with shuffles, level 3 on one
+// wavefront through LDS.  Edge tiles (and odd counts) run a generic path
+// that keeps the tile in LDS.  Deeper transforms chain passes through
+// scratch.
+//
+// Arithmetic: samples are widened to FP64, which gfx950 executes at the
+// rate of unpacked FP32.  One FP64 add replaces the six-operation pair sum
+// that keeps an FP32 approximation exact, the sums of 8 FP32 samples are
+// exact, and each output is rounded once to the storage type.  The
+// approximation grows by 2^(3/2) per level, so this matters more in 3D than
+// in 1D or 2D.
+#include <type_traits>
 #include <vector>
 
 #include "haar.h"
@@ -32,9 +40,8 @@ constexpr int kTZ = 8, kTY = 8, kTX = 64;       // generic tile
 constexpr int kMaxPassLevels3D = 3;            // log2 of the tile's shortest side
 constexpr int kTile = kTZ * kTY * kTX;         // 4096 samples
 constexpr int kThreads3 = 256;
-// (1/sqrt2)^3 = 1/(2 sqrt2) as a pair; halving the 1/sqrt2 pair is exact
-constexpr float kC3Hi = kRs2Hi * 0.5f;
-constexpr float kC3Lo = kRs2Lo * 0.5f;
+constexpr double kRs2d = kRsqrt2;               // b00 = a00 = 1/sqrt2
+constexpr double kC3 = kRsqrt2 * 0.5;           // (1/sqrt2)^3 = 1/(2 sqrt2)
 
 struct Pass3D {
     // analysis: src (region) -> det (bands) + ll (deepest LLL of the pass)
@@ -52,26 +59,22 @@ struct Pass3D {
     int64_t nfull, nedge;                      // interior / other tiles, all items
 };
 
-__device__ __forceinline__ df df_neg(df a) { return {-a.hi, -a.lo}; }
-__device__ __forceinline__ df df_sub(df a, df b) { return df_add(a, df_neg(b)); }
-__device__ __forceinline__ df df_c3(df a) { return df_mul(a, kC3Hi, kC3Lo); }
-
-// Value access of a region, LLL or scratch buffer: storage type S, or
-// compensated pairs (DF) in scratch.
+// Value access of a region, LLL or scratch buffer: storage type S, or FP64
+// scratch (DF).
 template <class S, bool DF>
-__device__ __forceinline__ df ld_val(const void* base, int64_t i) {
+__device__ __forceinline__ double ld_val(const void* base, int64_t i) {
     if constexpr (DF)
-        return reinterpret_cast<const df*>(base)[i];
+        return reinterpret_cast<const double*>(base)[i];
     else
-        return df_from(S::ld(reinterpret_cast<const typename S::raw*>(base)[i]));
+        return (double)S::ld(reinterpret_cast<const typename S::raw*>(base)[i]);
 }
 
 template <class S, bool DF>
-__device__ __forceinline__ void st_val(void* base, int64_t i, df v) {
+__device__ __forceinline__ void st_val(void* base, int64_t i, double v) {
     if constexpr (DF)
-        reinterpret_cast<df*>(base)[i] = v;
+        reinterpret_cast<double*>(base)[i] = v;
     else
-        st1_cached<S>(reinterpret_cast<typename S::raw*>(base) + i, df_round(v));
+        st1_cached<S>(reinterpret_cast<typename S::raw*>(base) + i, (float)v);
 }
 
 // Butterflies over the three axes of a 2 x 2 x 2 block, index dx | dy<<1 |
@@ -79,34 +82,17 @@ __device__ __forceinline__ void st_val(void* base, int64_t i, df v) {
 // high-pass along the axes whose bit is set in c (pair: (v0 + v1, v1 - v0));
 // synthesis applies the transposed stages ((a - d, a + d)).  Multiplying by
 // 1/(2 sqrt2) gives the orthonormal values.
-template <bool INV>
-__device__ __forceinline__ void bfly8(float* q) {
+template <bool INV, class T>
+__device__ __forceinline__ void bfly8(T* q) {
 #pragma unroll
     for (int bit = 1; bit < 8; bit <<= 1)
 #pragma unroll
         for (int i = 0; i < 8; ++i)
             if (!(i & bit)) {
-                const float a = q[i], b = q[i | bit];
+                const T a = q[i], b = q[i | bit];
                 q[i] = INV ? a - b : a + b;
                 q[i | bit] = INV ? a + b : b - a;
             }
-}
-
-template <bool INV>
-__device__ __forceinline__ void bfly8_df(df* q) {
-#pragma unroll
-    for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            if (!(i & bit)) {
-                const df a = q[i], b = q[i | bit];
-                q[i] = INV ? df_sub(a, b) : df_add(a, b);
-                q[i | bit] = INV ? df_add(a, b) : df_sub(b, a);
-            }
-}
-
-__device__ __forceinline__ df shfl_xor_pair(df a, int m) {
-    return df{__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)};
 }
 
 // Sizes of the LLL region after level j of the pass; the high halves of the
@@ -120,7 +106,7 @@ __device__ __forceinline__ Level3 level_sizes(const Pass3D& p, int j) {
 }
 
 // ---------------------------------------------------------------------------
-// Generic path: the tile in LDS as pairs, one 1D level per axis and level.
+// Generic path: the tile in LDS (FP64), one 1D level per axis and level.
 // ---------------------------------------------------------------------------
 
 // One analysis (INV = false) or synthesis level along axis A (0 x, 1 y, 2 z)
@@ -128,11 +114,11 @@ __device__ __forceinline__ Level3 level_sizes(const Pass3D& p, int j) {
 // 2048 (line, pair) slots of a full tile are dealt 8 per thread; the values
 // are read into registers, then written back after a barrier.
 template <int A, bool INV>
-__device__ __forceinline__ void lds_level(df* sm, int nz, int ny, int nx) {
+__device__ __forceinline__ void lds_level(double* sm, int nz, int ny, int nx) {
     const int n = A == 0 ? nx : (A == 1 ? ny : nz);
     const int pairs = n >> 1, na = n - pairs;
     constexpr int st = A == 0 ? 1 : (A == 1 ? kTX : kTX * kTY);
-    df u[8], v[8];
+    double u[8], v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int i = threadIdx.x + kThreads3 * k;
@@ -145,13 +131,13 @@ __device__ __forceinline__ void lds_level(df* sm, int nz, int ny, int nx) {
         if (act) {
             if (m < pairs) {
                 if (!INV) {
-                    const df x0 = sm[b + 2 * m * st], x1 = sm[b + (2 * m + 1) * st];
-                    u[k] = df_rs2(df_add(x0, x1));            // Eq. (11)
-                    v[k] = df_rs2(df_sub(x1, x0));            // Eq. (12)
+                    const double x0 = sm[b + 2 * m * st], x1 = sm[b + (2 * m + 1) * st];
+                    u[k] = (x0 + x1) * kRs2d;                 // Eq. (11)
+                    v[k] = (x1 - x0) * kRs2d;                 // Eq. (12)
                 } else {
-                    const df a = sm[b + m * st], d = sm[b + (na + m) * st];
-                    u[k] = df_rs2(df_sub(a, d));              // Eq. (19), even phase
-                    v[k] = df_rs2(df_add(a, d));              // odd phase
+                    const double a = sm[b + m * st], d = sm[b + (na + m) * st];
+                    u[k] = (a - d) * kRs2d;                   // Eq. (19), even phase
+                    v[k] = (a + d) * kRs2d;                   // odd phase
                 }
             } else {
                 u[k] = INV ? sm[b + (na - 1) * st] : sm[b + (n - 1) * st];   // carry
@@ -225,7 +211,7 @@ __device__ __forceinline__ TilePos tile_pos(int k) {
 // Detail octants of level j between LDS and the packed volume.
 template <class S, bool LOAD>
 __device__ __forceinline__ void lds_details(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
-                                            int64_t ox, const Counts3& c, int j, df* sm) {
+                                            int64_t ox, const Counts3& c, int j, double* sm) {
     const Level3 L = level_sizes(p, j);
     const int nz = c.cz(j - 1), ny = c.cy(j - 1), nx = c.cx(j - 1);
     const int az = c.cz(j), ay = c.cy(j), ax = c.cx(j);
@@ -242,14 +228,14 @@ __device__ __forceinline__ void lds_details(const Pass3D& p, int64_t item, int64
         if (LOAD)
             r[k] = ld1<S>(det + g);
         else
-            st1_cached<S>(det + g, df_round(sm[t.i]));
+            st1_cached<S>(det + g, (float)sm[t.i]);
     }
     if (LOAD) {
 #pragma unroll
         for (int k = 0; k < kPerThread3; ++k) {
             const TilePos t = tile_pos(k);
             if (t.z < nz && t.y < ny && t.x < nx && !(t.z < az && t.y < ay && t.x < ax))
-                sm[t.i] = df_from(r[k]);
+                sm[t.i] = (double)r[k];
         }
     }
 }
@@ -257,9 +243,9 @@ __device__ __forceinline__ void lds_details(const Pass3D& p, int64_t item, int64
 // Tile box [0, bz) x [0, by) x [0, bx) from a buffer (origin b, plane and row
 // strides) into LDS.
 template <class S, bool DF>
-__device__ __forceinline__ void lds_fill(df* sm, const void* src, int64_t b, int64_t sp, int64_t sr, int bz,
+__device__ __forceinline__ void lds_fill(double* sm, const void* src, int64_t b, int64_t sp, int64_t sr, int bz,
                                          int by, int bx) {
-    df r[kPerThread3];
+    double r[kPerThread3];
 #pragma unroll
     for (int k = 0; k < kPerThread3; ++k) {
         const TilePos t = tile_pos(k);
@@ -273,7 +259,7 @@ __device__ __forceinline__ void lds_fill(df* sm, const void* src, int64_t b, int
 }
 
 template <class S, bool DF>
-__device__ __forceinline__ void lds_drain(const df* sm, void* dst, int64_t b, int64_t sp, int64_t sr, int bz,
+__device__ __forceinline__ void lds_drain(const double* sm, void* dst, int64_t b, int64_t sp, int64_t sr, int bz,
                                           int by, int bx) {
 #pragma unroll
     for (int k = 0; k < kPerThread3; ++k) {
@@ -283,7 +269,7 @@ __device__ __forceinline__ void lds_drain(const df* sm, void* dst, int64_t b, in
 }
 
 template <class S, bool SRCDF, bool LLDF>
-__device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, df* sm) {
+__device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, double* sm) {
     const Counts3 c = tile_counts(p, oz, oy, ox);
     lds_fill<S, SRCDF>(sm, p.src, item * p.src_b + oz * p.src_p + oy * p.src_r + ox, p.src_p, p.src_r, c.z,
                        c.y, c.x);
@@ -301,7 +287,7 @@ __device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
 }
 
 template <class S, bool DSTDF, bool LLDF>
-__device__ void inv3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, df* sm) {
+__device__ void inv3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, double* sm) {
     const Counts3 c = tile_counts(p, oz, oy, ox);
     const int J = p.levels;
     lds_fill<S, LLDF>(sm, p.ll, item * p.ll_b + (oz >> J) * p.ll_p + (oy >> J) * p.ll_r + (ox >> J), p.ll_p,
@@ -350,8 +336,8 @@ __device__ __forceinline__ Map3 map3() {
 
 template <class S, bool RDF>
 struct Rx3 {
-    // samples per thread along x: 16 bytes of storage, or 4 pairs when the
-    // region is pair scratch (a deep pass)
+    // samples per thread along x: 16 bytes of storage, or 4 FP64 values
+    // when the region is scratch (a deep pass)
     static constexpr int RX = RDF ? 4 : 16 / S::kBytes;
     static constexpr int NB = RX / 2;          // level-1 blocks per thread
     static constexpr int NP = NB / 2;          // level-2 blocks per thread (along x)
@@ -360,7 +346,7 @@ struct Rx3 {
 };
 
 template <class S, bool RDF, int LV, bool LLDF>
-__device__ void fwd3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, df* sm) {
+__device__ void fwd3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, double* sm) {
     using raw = typename S::raw;
     using R = Rx3<S, RDF>;
     constexpr int RX = R::RX, NB = R::NB, NP = R::NP;
@@ -368,47 +354,41 @@ __device__ void fwd3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
     const int64_t sb = item * p.src_b + (oz + 2 * m.tz) * p.src_p + (oy + 2 * m.ty) * p.src_r + ox + RX * m.tx;
     raw* det = reinterpret_cast<raw*>(p.det) + item * p.det_b;
 
-    // level 1: NB blocks per thread; from storage the details are formed in
-    // FP32 and LLL as a pair, from pair scratch everything in pairs
-    const Level3 L1 = level_sizes(p, 1);
-    df lll[NB];
-    float d1[8][NB];
+    double v[2][2][RX];
     if constexpr (RDF) {
-        const df* src = reinterpret_cast<const df*>(p.src) + sb;
-        df v[2][2][RX];
+        const double* src = reinterpret_cast<const double*>(p.src) + sb;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
             for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
                 for (int e = 0; e < RX; ++e) v[dz][dy][e] = src[dz * p.src_p + dy * p.src_r + e];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            df q[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) q[i] = v[i >> 2][(i >> 1) & 1][2 * b + (i & 1)];
-            bfly8_df<false>(q);
-            lll[b] = df_c3(q[0]);
-#pragma unroll
-            for (int i = 1; i < 8; ++i) d1[i][b] = df_round(df_c3(q[i]));
-        }
     } else {
         const raw* src = reinterpret_cast<const raw*>(p.src) + sb;
-        float v[2][2][RX];
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-            for (int dy = 0; dy < 2; ++dy) ld_vec<S, RX>(src + dz * p.src_p + dy * p.src_r, v[dz][dy]);
+            for (int dy = 0; dy < 2; ++dy) {
+                float f[RX];
+                ld_vec<S, RX>(src + dz * p.src_p + dy * p.src_r, f);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            float q[8];
+                for (int e = 0; e < RX; ++e) v[dz][dy][e] = (double)f[e];
+            }
+    }
+
+    // level 1: NB blocks per thread
+    const Level3 L1 = level_sizes(p, 1);
+    double lll[NB];
+    float d1[8][NB];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) q[i] = v[i >> 2][(i >> 1) & 1][2 * b + (i & 1)];
-            lll[b] = df_c3(df_add(df_sum4f(q[0], q[1], q[2], q[3]), df_sum4f(q[4], q[5], q[6], q[7])));
-            bfly8<false>(q);
+    for (int b = 0; b < NB; ++b) {
+        double q[8];
 #pragma unroll
-            for (int i = 1; i < 8; ++i) d1[i][b] = q[i] * kC3Hi;
-        }
+        for (int i = 0; i < 8; ++i) q[i] = v[i >> 2][(i >> 1) & 1][2 * b + (i & 1)];
+        bfly8<false>(q);
+        lll[b] = q[0] * kC3;
+#pragma unroll
+        for (int i = 1; i < 8; ++i) d1[i][b] = (float)(q[i] * kC3);
     }
 #pragma unroll
     for (int c = 1; c < 8; ++c) {
@@ -421,30 +401,30 @@ __device__ void fwd3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
         const int64_t g = item * p.ll_b + ((oz >> 1) + m.tz) * p.ll_p + ((oy >> 1) + m.ty) * p.ll_r +
                           (ox >> 1) + NB * m.tx;
         if constexpr (LLDF) {
-            df* ll = reinterpret_cast<df*>(p.ll);
+            double* ll = reinterpret_cast<double*>(p.ll);
 #pragma unroll
             for (int b = 0; b < NB; ++b) ll[g + b] = lll[b];
         } else {
             float o[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) o[b] = df_round(lll[b]);
+            for (int b = 0; b < NB; ++b) o[b] = (float)lll[b];
             st_vec<S, NB>(reinterpret_cast<raw*>(p.ll) + g, o);
         }
         return;
     }
 
     // level 2: x in the thread, y with lane ^ 16, z with lane ^ 32
-    df s[NP], t[NP];
+    double s[NP], t[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-        s[q] = df_add(lll[2 * q], lll[2 * q + 1]);
-        t[q] = df_sub(lll[2 * q + 1], lll[2 * q]);
-        const df ps = shfl_xor_pair(s[q], 16), pt = shfl_xor_pair(t[q], 16);
-        s[q] = m.yo ? df_sub(s[q], ps) : df_add(s[q], ps);
-        t[q] = m.yo ? df_sub(t[q], pt) : df_add(t[q], pt);
-        const df zs = shfl_xor_pair(s[q], 32), zt = shfl_xor_pair(t[q], 32);
-        s[q] = df_c3(m.zo ? df_sub(s[q], zs) : df_add(s[q], zs));    // code (L, yo, zo)
-        t[q] = df_c3(m.zo ? df_sub(t[q], zt) : df_add(t[q], zt));    // code (H, yo, zo)
+        s[q] = lll[2 * q] + lll[2 * q + 1];
+        t[q] = lll[2 * q + 1] - lll[2 * q];
+        const double ps = __shfl_xor(s[q], 16), pt = __shfl_xor(t[q], 16);
+        s[q] = m.yo ? s[q] - ps : s[q] + ps;
+        t[q] = m.yo ? t[q] - pt : t[q] + pt;
+        const double zs = __shfl_xor(s[q], 32), zt = __shfl_xor(t[q], 32);
+        s[q] = (m.zo ? s[q] - zs : s[q] + zs) * kC3;     // code (L, yo, zo)
+        t[q] = (m.zo ? t[q] - zt : t[q] + zt) * kC3;     // code (H, yo, zo)
     }
     const Level3 L2 = level_sizes(p, 2);
     const int y2 = m.ty >> 1, z2 = m.tz >> 1;
@@ -455,8 +435,8 @@ __device__ void fwd3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
         raw* row = det + gz * p.det_p + gy * p.det_r + (ox >> 2) + NP * m.tx;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            st1_cached<S>(row + L2.W + q, df_round(t[q]));
-            if (!low) st1_cached<S>(row + q, df_round(s[q]));
+            st1_cached<S>(row + L2.W + q, (float)t[q]);
+            if (!low) st1_cached<S>(row + q, (float)s[q]);
         }
     }
     if constexpr (LV == 2) {
@@ -469,7 +449,7 @@ __device__ void fwd3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
         return;
     }
 
-    // level 3: LLL_2 of the tile (2 x 2 x X2) through LDS; 4 NP threads of
+    // level 3: LLL_2 of the tile (2 x 2 x X2) through LDS; X2 / 2 threads of
     // wavefront 0 each take one 2 x 2 x 2 block
     constexpr int X2 = R::X2;
     if (low) {
@@ -479,31 +459,31 @@ __device__ void fwd3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
     __syncthreads();
     if (threadIdx.x < X2 / 2) {
         const int k = threadIdx.x;
-        df q[8];
+        double q[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) q[i] = sm[((i >> 2) * 2 + ((i >> 1) & 1)) * X2 + 2 * k + (i & 1)];
-        bfly8_df<false>(q);
+        bfly8<false>(q);
         const Level3 L3 = level_sizes(p, 3);
 #pragma unroll
         for (int c = 1; c < 8; ++c) {
             const int64_t gz = ((c >> 2) ? L3.D : 0) + (oz >> 3);
             const int64_t gy = (((c >> 1) & 1) ? L3.H : 0) + (oy >> 3);
             const int64_t gx = ((c & 1) ? L3.W : 0) + (ox >> 3) + k;
-            st1_cached<S>(det + gz * p.det_p + gy * p.det_r + gx, df_round(df_c3(q[c])));
+            st1_cached<S>(det + gz * p.det_p + gy * p.det_r + gx, (float)(q[c] * kC3));
         }
         st_val<S, LLDF>(p.ll, item * p.ll_b + (oz >> 3) * p.ll_p + (oy >> 3) * p.ll_r + (ox >> 3) + k,
-                        df_c3(q[0]));
+                        q[0] * kC3);
     }
 }
 
 template <class S, bool RDF, int LV, bool LLDF>
-__device__ void inv3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, df* sm) {
+__device__ void inv3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, double* sm) {
     using raw = typename S::raw;
     using R = Rx3<S, RDF>;
     constexpr int RX = R::RX, NB = R::NB, NP = R::NP, X2 = R::X2;
     const Map3 m = map3();
     const raw* det = reinterpret_cast<const raw*>(p.det) + item * p.det_b;
-    df lll[NB];
+    double lll[NB];
     if constexpr (LV == 1) {
         const int64_t g = item * p.ll_b + ((oz >> 1) + m.tz) * p.ll_p + ((oy >> 1) + m.ty) * p.ll_r +
                           (ox >> 1) + NB * m.tx;
@@ -516,7 +496,7 @@ __device__ void inv3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
             if (threadIdx.x < X2 / 2) {
                 const int k = threadIdx.x;
                 const Level3 L3 = level_sizes(p, 3);
-                df q[8];
+                double q[8];
                 q[0] = ld_val<S, LLDF>(p.ll, item * p.ll_b + (oz >> 3) * p.ll_p + (oy >> 3) * p.ll_r +
                                                  (ox >> 3) + k);
 #pragma unroll
@@ -524,12 +504,12 @@ __device__ void inv3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
                     const int64_t gz = ((c >> 2) ? L3.D : 0) + (oz >> 3);
                     const int64_t gy = (((c >> 1) & 1) ? L3.H : 0) + (oy >> 3);
                     const int64_t gx = ((c & 1) ? L3.W : 0) + (ox >> 3) + k;
-                    q[c] = df_from(ld1<S>(det + gz * p.det_p + gy * p.det_r + gx));
+                    q[c] = (double)ld1<S>(det + gz * p.det_p + gy * p.det_r + gx);
                 }
-                bfly8_df<true>(q);
+                bfly8<true>(q);
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    sm[((i >> 2) * 2 + ((i >> 1) & 1)) * X2 + 2 * k + (i & 1)] = df_c3(q[i]);
+                    sm[((i >> 2) * 2 + ((i >> 1) & 1)) * X2 + 2 * k + (i & 1)] = q[i] * kC3;
             }
             __syncthreads();
         }
@@ -541,29 +521,27 @@ __device__ void inv3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
                            (ox >> 2) + NP * m.tx;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            df t = df_from(ld1<S>(row + L2.W + q));
-            df s;
+            double t = (double)ld1<S>(row + L2.W + q);
+            double s;
             if (!low) {
-                s = df_from(ld1<S>(row + q));
+                s = (double)ld1<S>(row + q);
             } else if constexpr (LV == 3) {
                 s = sm[(z2 * 2 + y2) * X2 + NP * m.tx + q];
             } else {
                 s = ld_val<S, LLDF>(p.ll, gl + q);
             }
             // undo z (lane ^ 32), then y (lane ^ 16): even member a - d, odd a + d
-            const df zs = shfl_xor_pair(s, 32), zt = shfl_xor_pair(t, 32);
-            s = m.zo ? df_add(zs, s) : df_sub(s, zs);
-            t = m.zo ? df_add(zt, t) : df_sub(t, zt);
-            const df ys = shfl_xor_pair(s, 16), yt = shfl_xor_pair(t, 16);
-            s = m.yo ? df_add(ys, s) : df_sub(s, ys);
-            t = m.yo ? df_add(yt, t) : df_sub(t, yt);
-            lll[2 * q] = df_c3(df_sub(s, t));
-            lll[2 * q + 1] = df_c3(df_add(s, t));
+            const double zs = __shfl_xor(s, 32), zt = __shfl_xor(t, 32);
+            s = m.zo ? zs + s : s - zs;
+            t = m.zo ? zt + t : t - zt;
+            const double ys = __shfl_xor(s, 16), yt = __shfl_xor(t, 16);
+            s = m.yo ? ys + s : s - ys;
+            t = m.yo ? yt + t : t - yt;
+            lll[2 * q] = (s - t) * kC3;
+            lll[2 * q + 1] = (s + t) * kC3;
         }
     }
 
-    // level 1: LLL_1 and the seven detail octants of the NB blocks, in FP32
-    // into storage, in pairs into pair scratch
     const Level3 L1 = level_sizes(p, 1);
     float d1[8][NB];
 #pragma unroll
@@ -573,38 +551,41 @@ __device__ void inv3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
         const int64_t gx = ((c & 1) ? L1.W : 0) + (ox >> 1) + NB * m.tx;
         ld_vec<S, NB>(det + gz * p.det_p + gy * p.det_r + gx, d1[c]);
     }
+    // level 1: LLL_1 and the seven detail octants of the NB blocks.  Samples
+    // rounded to 16 bits need no more than FP32 here (its error is 2^-16 of
+    // their spacing); FP32 and scratch outputs stay in FP64.
+    using TV = std::conditional_t<(S::kBytes == 2 && !RDF), float, double>;
+    TV v[2][2][RX];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        TV q[8];
+        q[0] = (TV)lll[b];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) q[i] = (TV)d1[i][b];
+        bfly8<true>(q);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i >> 2][(i >> 1) & 1][2 * b + (i & 1)] = q[i] * (TV)kC3;
+    }
     const int64_t db = item * p.dst_b + (oz + 2 * m.tz) * p.dst_p + (oy + 2 * m.ty) * p.dst_r + ox + RX * m.tx;
     if constexpr (RDF) {
-        df* dst = reinterpret_cast<df*>(p.dst) + db;
+        double* dst = reinterpret_cast<double*>(p.dst) + db;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            df q[8];
-            q[0] = lll[b];
+        for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-            for (int i = 1; i < 8; ++i) q[i] = df_from(d1[i][b]);
-            bfly8_df<true>(q);
+            for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                dst[(i >> 2) * p.dst_p + ((i >> 1) & 1) * p.dst_r + 2 * b + (i & 1)] = df_c3(q[i]);
-        }
+                for (int e = 0; e < RX; ++e) dst[dz * p.dst_p + dy * p.dst_r + e] = v[dz][dy][e];
     } else {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) d1[0][b] = df_round(lll[b]);
-        float v[2][2][RX];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            float q[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) q[i] = d1[i][b];
-            bfly8<true>(q);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) v[i >> 2][(i >> 1) & 1][2 * b + (i & 1)] = q[i] * kC3Hi;
-        }
         raw* dst = reinterpret_cast<raw*>(p.dst) + db;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-            for (int dy = 0; dy < 2; ++dy) st_vec<S, RX>(dst + dz * p.dst_p + dy * p.dst_r, v[dz][dy]);
+            for (int dy = 0; dy < 2; ++dy) {
+                float f[RX];
+#pragma unroll
+                for (int e = 0; e < RX; ++e) f[e] = (float)v[dz][dy][e];
+                st_vec<S, RX>(dst + dz * p.dst_p + dy * p.dst_r, f);
+            }
     }
 }
 
@@ -612,8 +593,8 @@ __device__ void inv3d_regs(const Pass3D& p, int64_t item, int64_t oz, int64_t oy
 // Kernels.  Interior tiles (the register path) and the other tiles (the LDS
 // path) are separate launches, so that each keeps its own register budget.
 // Tiles run x-fastest; a grid-stride loop covers grids beyond the cap.
-// RDF: the region (analysis source / synthesis destination) is pair
-// scratch; LDF: the pass's deepest LLL is pair scratch.
+// RDF: the region (analysis source / synthesis destination) is FP64
+// scratch; LDF: the pass's deepest LLL is FP64 scratch.
 // ---------------------------------------------------------------------------
 template <class S, bool RDF>
 __device__ __forceinline__ void full_origin(const Pass3D& p, int64_t t, int64_t& item, int64_t& oz,
@@ -661,7 +642,7 @@ __device__ __forceinline__ void edge_origin(const Pass3D& p, int64_t e, int64_t&
 
 template <class S, bool RDF, int LV, bool LDF>
 __global__ __launch_bounds__(kThreads3) void fwd3d_full_kernel(Pass3D p) {
-    __shared__ df sm[4 * Rx3<S, RDF>::X2];
+    __shared__ double sm[4 * Rx3<S, RDF>::X2];
     for (int64_t t = blockIdx.x; t < p.nfull; t += gridDim.x) {
         int64_t item, oz, oy, ox;
         full_origin<S, RDF>(p, t, item, oz, oy, ox);
@@ -672,7 +653,7 @@ __global__ __launch_bounds__(kThreads3) void fwd3d_full_kernel(Pass3D p) {
 
 template <class S, bool RDF, int LV, bool LDF>
 __global__ __launch_bounds__(kThreads3) void inv3d_full_kernel(Pass3D p) {
-    __shared__ df sm[4 * Rx3<S, RDF>::X2];
+    __shared__ double sm[4 * Rx3<S, RDF>::X2];
     for (int64_t t = blockIdx.x; t < p.nfull; t += gridDim.x) {
         int64_t item, oz, oy, ox;
         full_origin<S, RDF>(p, t, item, oz, oy, ox);
@@ -683,7 +664,7 @@ __global__ __launch_bounds__(kThreads3) void inv3d_full_kernel(Pass3D p) {
 
 template <class S, bool RDF, bool LDF>
 __global__ __launch_bounds__(kThreads3) void fwd3d_edge_kernel(Pass3D p) {
-    __shared__ df sm[kTile];
+    __shared__ double sm[kTile];
     for (int64_t t = blockIdx.x; t < p.nedge; t += gridDim.x) {
         int64_t item, oz, oy, ox;
         edge_origin(p, t, item, oz, oy, ox);
@@ -694,7 +675,7 @@ __global__ __launch_bounds__(kThreads3) void fwd3d_edge_kernel(Pass3D p) {
 
 template <class S, bool RDF, bool LDF>
 __global__ __launch_bounds__(kThreads3) void inv3d_edge_kernel(Pass3D p) {
-    __shared__ df sm[kTile];
+    __shared__ double sm[kTile];
     for (int64_t t = blockIdx.x; t < p.nedge; t += gridDim.x) {
         int64_t item, oz, oy, ox;
         edge_origin(p, t, item, oz, oy, ox);
@@ -775,16 +756,16 @@ int run_3d(const void* in, void* out, int64_t D, int64_t H, int64_t W, int L, in
         }
     }
     const int np = (int)ps.size();
-    // pair scratch between passes: two ping-pong buffers sized for the
+    // FP64 scratch between passes: two ping-pong buffers sized for the
     // region after the first pass
     void* scratch = nullptr;
     int64_t half = 0;
     if (np > 1) {
         half = batch * ps[1].d * ps[1].h * ps[1].w;
-        hipError_t e = hipMallocAsync(&scratch, (size_t)(2 * half * (int64_t)sizeof(float) * 2), s);
+        hipError_t e = hipMallocAsync(&scratch, (size_t)(2 * half * (int64_t)sizeof(double)), s);
         if (e != hipSuccess) return hip_error(e, "hipMallocAsync (3D pass scratch)");
     }
-    auto buf = [&](int k) -> void* { return (char*)scratch + ((k & 1) ? 0 : half) * 8; };
+    auto buf = [&](int k) -> void* { return (char*)scratch + ((k & 1) ? 0 : half) * (int64_t)sizeof(double); };
 
     int rc = HAAR_OK;
     for (int step = 0; step < np && rc == HAAR_OK; ++step) {
@@ -819,7 +800,7 @@ int run_3d(const void* in, void* out, int64_t D, int64_t H, int64_t W, int L, in
         p.nty = ceil_shift_host(r.h, 3);
         p.ntx = ceil_shift_host(r.w, 6);
         // interior tile width: 16 threads of 16 bytes of storage, or of 4
-        // pairs when the region is pair scratch
+        // FP64 values when the region is scratch
         const int ftx = 16 * (rdf ? 4 : 16 / elem_bytes(dtype));
         p.fz = r.d / kTZ;
         p.fy = r.h / kTY;

@@ -107,11 +107,18 @@ __device__ __forceinline__ float f_norm(float d, int j) {
 // ---------------------------------------------------------------------------
 // Storage formats.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// FP32 -> BF16 with round-to-nearest-even: gfx950's packed conversion
+// instruction (v_cvt_pk_bf16_f32) rounds two values at once; NaN stays NaN.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2(float a, float b) {
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 struct StF32 {
@@ -127,7 +134,8 @@ struct StBF16 {
     using raw = uint16_t;
     static constexpr int kBytes = 2;
     __device__ __forceinline__ static float ld(raw v) { return __uint_as_float((uint32_t)v << 16); }
-    __device__ __forceinline__ static raw st(float f) { return f32_to_bf16_rne(f); }
+    __device__ __forceinline__ static raw st(float f) { return f32_to_bf16(f); }
+    __device__ __forceinline__ static uint32_t st2(float a, float b) { return f32x2_to_bf16x2(a, b); }
 };
 
 // FP32 coefficients of one tile or chunk held on chip (a packed buffer in
@@ -149,6 +157,9 @@ struct StF16 {
     }
     __device__ __forceinline__ static raw st(float f) {
         return __builtin_bit_cast(uint16_t, (_Float16)f);
+    }
+    __device__ __forceinline__ static uint32_t st2(float a, float b) {
+        return (uint32_t)st(a) | ((uint32_t)st(b) << 16);
     }
 };
 
@@ -252,7 +263,7 @@ __device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {
             uint32_t w[B / 4];
 #pragma unroll
             for (int i = 0; i < N / 2; ++i)
-                w[i] = (uint32_t)S::st(v[2 * i]) | ((uint32_t)S::st(v[2 * i + 1]) << 16);
+                w[i] = S::st2(v[2 * i], v[2 * i + 1]);
             if constexpr (B == 16) {
                 v4u o = {w[0], w[1], w[2], w[3]};
                 st_s<S>(o, reinterpret_cast<v4u*>(p));
