@@ -374,8 +374,22 @@ def suite():
     res["note"] = "GB/s = algorithmic bytes (read + write once) / time"
     print(json.dumps(res), flush=True)
 
-    # 8) separable 3D on CT-like volumes: 4 x 256^3, 3 levels (one fused
-    #    pass) in FP32 and BF16, and full depth (8 levels, three passes)
+    # 8) separable 3D on CT-like volumes
+    volumes()
+
+
+def volumes():
+    """Separable 3D on CT-like volumes: 4 x 256^3, 3 levels (one fused pass)
+    in FP32 and BF16, and full depth (8 levels, three passes), beside a
+    torch copy of the same bytes.  One JSON line per case."""
+    import torch
+
+    from paper_1002_2184_amd import transform as T
+    from workloads import generators as G
+
+    dev = torch.device("cuda", 0)
+    st = torch.cuda.current_stream(dev)
+    kk = [0]
     vol = torch.from_numpy(G.to_storage(G.phantom_volume(G.rng_for(8), 256, 256, 256), G.F32)).to(dev)
     gen = torch.Generator(device=dev)
     gen.manual_seed(G.SEED + 8)
@@ -440,9 +454,14 @@ def main():
                     help="summarise a rocprofv3 kernel stats CSV into a Markdown table")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads (1D latency, batched, autograd, BF16) and exit")
+    ap.add_argument("--volumes", action="store_true",
+                    help="measure only the 3D volume workloads of the suite and exit")
     args = ap.parse_args()
     if args.suite:
         suite()
+        return
+    if args.volumes:
+        volumes()
         return
     if args.write_kernel_stats:
         write_kernel_stats(*args.write_kernel_stats)

@@ -49,10 +49,11 @@
  *   enqueues nothing and returns HAAR_OK.
  * Threading.  All entry points are reentrant; the tuning table is guarded by
  *   a mutex.
- * Scratch.  Most calls allocate nothing.  Three cases keep intermediate
+ * Scratch.  Most calls allocate nothing.  Four cases keep intermediate
  *   values in stream-ordered scratch obtained with hipMallocAsync on `stream`
  *   and released with hipFreeAsync on the same stream: 2D transforms deeper
- *   than one fused pass (levels > 5); 1D analyses deeper than one chunk
+ *   than one fused pass (levels > 5); 3D transforms deeper than one fused
+ *   pass (levels > 3); 1D analyses deeper than one chunk
  *   (levels > 12 at the default 4096-sample chunk) in BF16/FP16 storage (one
  *   FP32 value per chunk) or on more than 1024 chunks per signal; and 1D
  *   syntheses more than 24 levels deeper than one chunk.
