@@ -18,6 +18,9 @@ Functions (all float64 in, float64 out, out-of-place, same shape):
   ``[..., h, w]``: rows then columns per level, recursion on LL.
 * ``fwd_3d(x, levels)`` / ``inv_3d(y, levels)`` -- separable 3D on
   ``[..., d, h, w]``: x, then y, then z per level, recursion on LLL.
+* ``l1_grad_2d(x, levels)`` -- loss sum |details| + 0.5 ||LL_L||^2 of the
+  2D analysis and its gradient with respect to x (synthesis of the
+  coefficient gradient).
 * ``filter_taps()`` -- the taps (b0, b1, a0, a1) of Eq. (8), (9), (17), (18).
 """
 from __future__ import annotations
@@ -73,6 +76,8 @@ class Oracle:
             fn = getattr(lib, name)
             fn.argtypes = [P, P, i64, i64, i64, i32, i64]
             fn.restype = None
+        lib.oracle_l1_grad_2d.argtypes = [P, P, P, i64, i64, i32, i64]
+        lib.oracle_l1_grad_2d.restype = None
         lib.oracle_shrink_1d.argtypes = [P, P, i64, i32, i64, i32, P]
         lib.oracle_shrink_1d.restype = None
         lib.oracle_shrink_2d.argtypes = [P, P, i64, i64, i32, i64, i32, P]
@@ -145,6 +150,20 @@ class Oracle:
     def inv_3d(self, y, levels):
         """Separable multi-level 3D synthesis (z, y, x per level, levels L..1)."""
         return self._call_3d("oracle_inv_3d", y, levels)
+
+    def l1_grad_2d(self, x, levels):
+        """(loss per item, grad_x) of loss = sum |details| + 0.5 * ||LL_L||^2
+        of the 2D analysis of x; grad_x = synthesis of (sign(details), LL_L)."""
+        _check_levels(levels)
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        if x.ndim < 2 or min(x.shape[-2:]) < 1:
+            raise ValueError("2D oracle needs non-empty last two axes")
+        h, w = x.shape[-2], x.shape[-1]
+        g = np.empty_like(x)
+        batch = x.size // (h * w)
+        loss = np.empty(batch, dtype=np.float64)
+        self.lib.oracle_l1_grad_2d(_ptr(x), _ptr(g), _ptr(loss), h, w, int(levels), batch)
+        return loss.reshape(x.shape[:-2]), g
 
     def _thresholds(self, levels, thresholds):
         t = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float64).reshape(-1))
@@ -248,6 +267,10 @@ def band_slices_3d(d: int, h: int, w: int, levels: int):
                     code = ("H" if bx else "L") + ("H" if by else "L") + ("H" if bz else "L")
                     sl[(code, j)] = (zs, ys, xs)
     return sl
+
+
+def l1_grad_2d(x, levels: int):
+    return default().l1_grad_2d(x, levels)
 
 
 def shrink_1d(x, levels: int, mode: int, thresholds) -> np.ndarray:

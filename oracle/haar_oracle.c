@@ -40,6 +40,9 @@
  *   - odd lengths ("carry rule"): when a level sees an odd count, its last
  *     sample passes unscaled into the approximation; there is no detail
  *     for it.  ceil(n/2) approximations, floor(n/2) details.
+ *   - the sparsity loss of a training step through the 2D transform, sum of
+ *     |details| + 0.5 ||LL_L||^2, and its gradient (the synthesis bank
+ *     applied to the coefficient gradient, since W^T = W^-1);
  *   - 3D (volumes [batch][d][h][w], the paper's medical-image use): the 2D
  *     reading extended by one axis; per level one 1D level along x (width),
  *     then y (height), then z (depth) on the current LLL region, recursion
@@ -446,6 +449,41 @@ void oracle_shrink_2d(const double* x, double* y, int64_t h, int64_t w,
                     if (r >= lh[j] || q >= lw[j])
                         c[r * w + q] = shrink_value(c[r * w + q], mode, thr[j - 1]);
         inv_2d_item(c, y + b * h * w, h, w, levels);
+    }
+    free(c);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sparsity loss of a training step through the 2D transform and its       */
+/* gradient:  c = W x (analysis),  loss = sum |details of levels 1..L|     */
+/* + 0.5 * sum LL_L^2,  dloss/dc = (sign(details), LL_L) with sign(0) = 0, */
+/* grad_x = W^T dloss/dc, and W^T = W^-1 is the synthesis bank (Sec. IV).  */
+/* loss: one value per item.                                               */
+/* ---------------------------------------------------------------------- */
+void oracle_l1_grad_2d(const double* x, double* g, double* loss, int64_t h,
+                       int64_t w, int32_t levels, int64_t batch)
+{
+    double* c = (double*)malloc((size_t)(h * w) * sizeof(double));
+    int64_t hL = h, wL = w;                 /* size of LL_L             */
+    for (int j = 1; j <= levels; ++j) {
+        hL = (hL + 1) / 2;
+        wL = (wL + 1) / 2;
+    }
+    for (int64_t b = 0; b < batch; ++b) {
+        fwd_2d_item(x + b * h * w, c, h, w, levels);
+        double l = 0.0;
+        for (int64_t r = 0; r < h; ++r)
+            for (int64_t q = 0; q < w; ++q) {
+                double* v = &c[r * w + q];
+                if (r < hL && q < wL) {
+                    l += 0.5 * *v * *v;                        /* LL_L      */
+                } else {
+                    l += fabs(*v);                             /* a detail  */
+                    *v = *v > 0.0 ? 1.0 : (*v < 0.0 ? -1.0 : 0.0);
+                }
+            }
+        loss[b] = l;
+        inv_2d_item(c, g + b * h * w, h, w, levels);
     }
     free(c);
 }

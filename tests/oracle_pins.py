@@ -1,7 +1,7 @@
 """Pins of the FP64 oracle against what the paper and the mathematics fix.
 
 Each ``pin_*`` takes an oracle object (``oracle.Oracle``: fwd_1d, inv_1d,
-direct_fwd_1d, direct_inv_1d, fwd_2d, inv_2d, fwd_3d, inv_3d, filter_taps) and raises
+direct_fwd_1d, direct_inv_1d, fwd_2d, inv_2d, fwd_3d, inv_3d, l1_grad_2d, filter_taps) and raises
 AssertionError when it disagrees.  None of them re-types the oracle's loops:
 they compare it with closed forms, hand-derived fixtures, an independent
 formulation (the direct filter bank), polynomial identities of the filter
@@ -462,10 +462,60 @@ def pin_3d_invariants(orc):
         _close(orc.inv_3d(y, L), x, 1e-13, f"3D PR {d}x{h}x{w}")
 
 
+# ---------------------------------------------------------------------------
+# Gradient of the sparsity loss through the 2D transform.
+
+
+def pin_l1_grad_matrix(orc):
+    """With W the closed-form 2D Haar matrix (dyadic sizes) and c = W x:
+    loss = sum |c_details| + 0.5 sum c_LL^2 and grad_x = W^T (sign(c_details),
+    c_LL)."""
+    rng = np.random.default_rng(37)
+    for (h, w, L) in [(4, 4, 1), (8, 8, 3), (16, 8, 2), (8, 16, 3)]:
+        W = haar_matrix_2d_dyadic(h, w, L)
+        x = rng.standard_normal((3, h, w))
+        loss, g = orc.l1_grad_2d(x, L)
+        ll = np.zeros((h, w), bool)
+        ll[:h >> L, :w >> L] = True
+        llv = ll.ravel()
+        for b in range(3):
+            c = W @ x[b].ravel()
+            want_loss = np.sum(np.abs(c[~llv])) + 0.5 * np.sum(c[llv] ** 2)
+            s = np.where(llv, c, np.sign(c))
+            _close(loss[b], want_loss, 1e-13, f"l1 loss {h}x{w} L={L}")
+            _close(g[b].ravel(), W.T @ s, 1e-13, f"l1 grad {h}x{w} L={L}")
+
+
+def pin_l1_grad_finite_differences(orc):
+    """Central differences of the oracle's own loss match its gradient on odd
+    and even sizes (the loss is smooth away from zero coefficients; indices
+    whose step would move a detail across zero are skipped)."""
+    rng = np.random.default_rng(41)
+    eps = 1e-6
+    for (h, w, L) in [(5, 7, 2), (9, 6, 3), (8, 8, 3), (3, 11, 1)]:
+        x = rng.standard_normal((h, w))
+        loss, g = orc.l1_grad_2d(x, L)
+        c = orc.fwd_2d(x, L)
+        checked = 0
+        for i in rng.permutation(h * w)[:20]:
+            e = np.zeros(h * w)
+            e[i] = eps
+            e = e.reshape(h, w)
+            cp, cm = orc.fwd_2d(x + e, L), orc.fwd_2d(x - e, L)
+            if np.any(np.sign(cp) != np.sign(c)) or np.any(np.sign(cm) != np.sign(c)):
+                continue
+            fd = (orc.l1_grad_2d(x + e, L)[0] - orc.l1_grad_2d(x - e, L)[0]) / (2 * eps)
+            assert abs(fd - g.ravel()[i]) <= 1e-6 * max(1.0, abs(g.ravel()[i])), \
+                f"l1 FD {h}x{w} L={L} index {i}: {fd} vs {g.ravel()[i]}"
+            checked += 1
+        assert checked >= 10, f"too few FD indices away from kinks ({checked})"
+
+
 ALL_PINS = [
     pin_paper_coefficients, pin_worked_examples, pin_dyadic_closed_form, pin_carry_weights,
     pin_carry_impulse, pin_orthonormal_and_inverse, pin_direct_equals_fast, pin_alias_free_taps,
     pin_constant, pin_parseval_and_pr, pin_2d_separable, pin_2d_dyadic_closed_form,
     pin_locality, pin_adjoint, pin_shrink_matrix, pin_shrink_extremes, pin_shrink_hard_projection,
-    pin_3d_separable, pin_3d_reductions, pin_3d_invariants,
+    pin_3d_separable, pin_3d_reductions, pin_3d_invariants, pin_l1_grad_matrix,
+    pin_l1_grad_finite_differences,
 ]

@@ -61,6 +61,10 @@ MUTANTS = {
     "shrink_2d_only_hh": ("if (r >= lh[j] || q >= lw[j])", "if (r >= lh[j] && q >= lw[j])"),
     "2d_row_skips_last": ("for (int64_t r = 0; r < ch; ++r) {            /* rows (width)   */",
                           "for (int64_t r = 0; r < ch - 1; ++r) {            /* rows (width)   */"),
+    "l1_loss_ll_factor": ("l += 0.5 * *v * *v;", "l += *v * *v;"),
+    "l1_ll_treated_as_detail": ("if (r < hL && q < wL) {", "if (r < hL && q < wL && 0) {"),
+    "l1_detail_gradient_sign": ("*v = *v > 0.0 ? 1.0 : (*v < 0.0 ? -1.0 : 0.0);",
+                                "*v = *v > 0.0 ? -1.0 : (*v < 0.0 ? 1.0 : 0.0);"),
     "3d_depth_floor": ("cd = (cd + 1) / 2;", "cd = cd / 2;"),
     "3d_z_pass_skipped": ("lines_3d(v, h, w, cd, ch, cw, 2, 0);", "/* z pass dropped */"),
     "3d_inverse_sizes": ("ld[j] = (ld[j - 1] + 1) / 2;", "ld[j] = ld[j - 1] / 2;"),
