@@ -256,6 +256,27 @@ def suite():
                       "gbps_fwd_bwd": round(4 * n4 * 4 / (ms_ag * 1e-3) / 1e9, 1),
                       "gbps_plain_fwd_inv": round(4 * n4 * 4 / (ms_pl * 1e-3) / 1e9, 1),
                       "ms_fwd_bwd": round(ms_ag, 4), "ms_plain": round(ms_pl, 4)}), flush=True)
+
+    # 3b) the whole training step of the sparsity loss sum|details| +
+    #     0.5||LL_3||^2: autograd with the loss in torch, against the fused
+    #     one-pass kernel (loss and gradient)
+    ll_mask = torch.zeros(512, 512, dtype=torch.bool, device=dev)
+    ll_mask[:64, :64] = True
+    det_mask = ~ll_mask
+
+    def step_unfused():
+        y = AG.HaarFwd2D.apply(xa, 3)
+        loss = (y.abs() * det_mask).sum() + 0.5 * (y * y * ll_mask).sum()
+        torch.autograd.grad(loss, xa)
+    ms_un = _timed(step_unfused, 10, 2, st)
+
+    def step_fused():
+        T.l1_grad2d(xd, 3, out=za)
+    ms_fu = _timed(step_fused, 20, 3, st)
+    print(json.dumps({"workload": "2d-64x3x512x512-L3 sparsity-loss training step (loss + grad)",
+                      "ms_autograd_torch_loss": round(ms_un, 4), "ms_fused": round(ms_fu, 4),
+                      "gbps_fused_one_pass": round(2 * n4 * 4 / (ms_fu * 1e-3) / 1e9, 1),
+                      "speedup": round(ms_un / ms_fu, 2)}), flush=True)
     del xa, ga, ya, za, xd
     torch.cuda.empty_cache()
 

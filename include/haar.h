@@ -49,7 +49,8 @@
  *   enqueues nothing and returns HAAR_OK.
  * Threading.  All entry points are reentrant; the tuning table is guarded by
  *   a mutex.
- * Scratch.  Most calls allocate nothing.  Four cases keep intermediate
+ * Scratch.  Most calls allocate nothing.  haar_l1_grad_2d keeps its tile
+ *   loss partials in stream-ordered scratch.  Four more cases keep intermediate
  *   values in stream-ordered scratch obtained with hipMallocAsync on `stream`
  *   and released with hipFreeAsync on the same stream: 2D transforms deeper
  *   than one fused pass (levels > 5); 3D transforms deeper than one fused
@@ -178,6 +179,25 @@ int haar_shrink_1d(const void* x, void* y, int64_t length, int32_t levels,
 int haar_shrink_2d(const void* x, void* y, int64_t height, int64_t width,
                    int32_t levels, int64_t batch, int32_t dtype, int32_t mode,
                    const float* thresholds, void* stream);
+
+/* Fused training step of a sparsity loss through the 2D transform, in ONE
+ * pass over HBM.  With c = W x the analysis of each item (haar_fwd_2d):
+ *   loss  = sum |c| over the detail bands of levels 1..L
+ *           + 0.5 * sum c^2 over LL_L,
+ *   dloss/dc = sign(c) on the details (sign(0) = 0), c on LL_L,
+ *   grad_x = W^T dloss/dc, the synthesis bank (Sec. IV, Eq. (19)) applied
+ *            to dloss/dc: the transform is orthonormal, W^T = W^-1.
+ * x, grad_x: [batch][height][width] device tensors of `dtype`, caller-owned,
+ * not overlapping.  loss: device array of `batch` doubles, one loss per
+ * item, written by the call (the tile partial sums are reduced in a fixed
+ * order, so repeated calls agree bit for bit).  1 <= levels <=
+ * min(5, haar_max_levels_2d): HAAR_ERR_LEVELS beyond the transform's depth,
+ * HAAR_ERR_UNSUPPORTED for levels 0 or beyond one fused tile (5).  Uses
+ * stream-ordered scratch of 8 bytes per tile (about 8 bytes per 8192 FP32
+ * elements). */
+int haar_l1_grad_2d(const void* x, void* grad_x, double* loss, int64_t height,
+                    int64_t width, int32_t levels, int64_t batch,
+                    int32_t dtype, void* stream);
 
 /* ------------------------------------------------------------------------
  * The direct ("original") filter bank, for comparison with the fast bank.

@@ -45,6 +45,11 @@ constexpr int kShrinkChunk = 4096, kShrinkChunkThreads = 256;
 constexpr int kMaxShrinkLevels2D = 5;
 int run_shrink_1d(const void* in, void* out, int64_t n, int L, int64_t batch, int dtype, int mode,
                   const float* thr, hipStream_t s);
+// Fused training step of the sparsity loss sum |details| + 0.5 ||LL_L||^2
+// through the 2D transform: gradient with respect to the input and the
+// loss of each item (levels <= 5).
+int run_l1_grad_2d(const void* in, void* out, double* loss, int64_t h, int64_t w, int L, int64_t batch,
+                   int dtype, hipStream_t s);
 // Direct (convolve-then-decimate) structure, for comparison with the fast bank.
 size_t direct_workspace_floats(int64_t n, int64_t batch);
 int run_direct_1d(const void* in, void* out, int64_t n, int L, int64_t batch, int dtype, bool inverse,

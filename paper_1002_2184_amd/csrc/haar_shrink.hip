@@ -17,6 +17,14 @@
 //   3. the synthesis device code reads the buffer and writes the output.
 // HBM traffic: the input once, the output once.
 //
+// The same 2D pipeline also runs one training step of the sparsity loss
+// sum |details| + 0.5 ||LL_L||^2 (OP = kOpL1): the coefficient operation is
+// then the loss gradient (sign of each detail, LL_L itself), the synthesis
+// of it is the gradient with respect to the input (the synthesis bank is
+// the transpose of the analysis), and every tile adds its share of the
+// loss to a per-tile partial sum, reduced per item afterwards in a fixed
+// order.
+//
 // Full 2D tiles and full 1D chunks take register paths instead: the
 // synthesis of a thread's block needs exactly the details that the analysis
 // of the same block produced, so those stay in registers (thresholded in
@@ -31,12 +39,51 @@ namespace haar {
 struct ShrinkArgs {
     float thr[kMaxShrinkLevels];
     int mode;
+    double* partial;                         // kOpL1: one loss partial per tile
 };
 
 __device__ __forceinline__ float shrink_value(float d, int mode, float t) {
     if (mode == 0) return fabsf(d) > t ? d : 0.0f;
     const float m = fabsf(d) - t;
     return m > 0.0f ? copysignf(m, d) : 0.0f;
+}
+
+// Coefficient operations of the 2D pipeline.
+constexpr int kOpShrink = 0, kOpL1 = 1;
+
+// A detail coefficient: thresholded, or replaced by its loss gradient
+// sign(d) (sign(0) = 0) while |d| joins the loss.
+template <int OP>
+__device__ __forceinline__ float detail_op(float d, int mode, float t, float& acc) {
+    if constexpr (OP == kOpShrink) {
+        return shrink_value(d, mode, t);
+    } else {
+        acc += fabsf(d);
+        return d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+    }
+}
+
+// LL_L: kept (its loss gradient is itself); 0.5 LL^2 joins the loss.
+template <int OP>
+__device__ __forceinline__ void ll_op(float v, float& acc) {
+    if constexpr (OP == kOpL1) acc += 0.5f * v * v;
+}
+
+// Sum of the work-group's loss shares into partial[slot] (FP64, fixed order).
+template <int NT>
+__device__ __forceinline__ void tile_loss(float acc, double* partial, int64_t slot) {
+    __shared__ double red[NT / 64];
+    double v = (double)acc;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < NT / 64; ++i) t += red[i];
+        partial[slot] = t;
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -227,11 +274,12 @@ __global__ __launch_bounds__(NT) void shrink1d_full_kernel(const void* x, void* 
 // Partial tiles (right column, bottom row), LDS-buffer path: edge tile e of
 // an item is (ty = e, tx = full_x) for e < right, else (ty = full_y,
 // tx = e - right).
-template <class S, int GY, int GX>
+template <class S, int GY, int GX, int OP>
 __global__ __launch_bounds__(GY* GX) void shrink2d_edge_kernel(const void* x, void* y, int64_t h, int64_t w,
                                                                int L, int64_t full_x, int64_t full_y,
                                                                int64_t right, int64_t bottom,
-                                                               int64_t total, ShrinkArgs sh) {
+                                                               int64_t total, ShrinkArgs sh,
+                                                               int64_t slot0) {
     constexpr int RX = 16 / S::kBytes;
     using G = Geo2D<S, 4, RX, GY, GX>;
     using In = InvInT<S, StLds, StLds, 4, RX, GY, GX>;
@@ -268,13 +316,19 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_edge_kernel(const void* x, vo
         }
         __syncthreads();
         // level j bands: inside the level-(j-1) LL region, outside level j's
+        float acc = 0.0f;
         for (int e = threadIdx.x; e < th * tw; e += NT) {
             const int rr = e / tw, cc = e - rr * tw;
             int j = 1;
             while (j <= L && rr < ceil_shift(th, j) && cc < ceil_shift(tw, j)) ++j;
-            if (j <= L) buf[rr * TW + cc] = shrink_value(buf[rr * TW + cc], sh.mode, thr[j - 1]);
+            float& c = buf[rr * TW + cc];
+            if (j <= L)
+                c = detail_op<OP>(c, sh.mode, thr[j - 1], acc);
+            else
+                ll_op<OP>(c, acc);
         }
         __syncthreads();
+        if constexpr (OP == kOpL1) tile_loss<NT>(acc, sh.partial, slot0 + b);
         p.dst = reinterpret_cast<typename S::raw*>(y) + origin;
         p.dst_pitch = w;
         {
@@ -287,7 +341,7 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_edge_kernel(const void* x, vo
 }
 
 // Full tiles, register path.  LL2 region of the tile: RH x RW = (TH/4) x (TW/4).
-template <class S, int GY, int GX>
+template <class S, int GY, int GX, int OP>
 __global__ __launch_bounds__(GY* GX) void shrink2d_full_kernel(const void* x, void* y, int64_t h,
                                                                int64_t w, int L, int64_t full_x,
                                                                int64_t full_y, int64_t total,
@@ -316,6 +370,7 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_full_kernel(const void* x, vo
         float v[RY][RX];
 #pragma unroll
         for (int i = 0; i < RY; ++i) ld_vec<S, RX>(src + (int64_t)(lr0 + i) * w + lc0, v[i]);
+        float acc = 0.0f;                    // this thread's share of the loss (kOpL1)
 
         // ---- analysis, levels 1 and 2 (details thresholded in registers)
         df a1[B1Y][B1X];
@@ -326,16 +381,19 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_full_kernel(const void* x, vo
             for (int k = 0; k < B1X; ++k) {
                 ana_full_f(v[2 * i][2 * k], v[2 * i][2 * k + 1], v[2 * i + 1][2 * k], v[2 * i + 1][2 * k + 1],
                            a1[i][k], hl1[i][k], lh1[i][k], hh1[i][k]);
-                hl1[i][k] = shrink_value(hl1[i][k], mode, t1);
-                lh1[i][k] = shrink_value(lh1[i][k], mode, t1);
-                hh1[i][k] = shrink_value(hh1[i][k], mode, t1);
+                hl1[i][k] = detail_op<OP>(hl1[i][k], mode, t1, acc);
+                lh1[i][k] = detail_op<OP>(lh1[i][k], mode, t1, acc);
+                hh1[i][k] = detail_op<OP>(hh1[i][k], mode, t1, acc);
             }
         float ll1[B1Y][B1X];
         if (L == 1) {
 #pragma unroll
             for (int i = 0; i < B1Y; ++i)
 #pragma unroll
-                for (int k = 0; k < B1X; ++k) ll1[i][k] = df_round(a1[i][k]);
+                for (int k = 0; k < B1X; ++k) {
+                    ll1[i][k] = df_round(a1[i][k]);
+                    ll_op<OP>(ll1[i][k], acc);
+                }
         } else {
             df a2[B2X];
             float hl2[B2X], lh2[B2X], hh2[B2X], ll2[B2X];
@@ -343,10 +401,11 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_full_kernel(const void* x, vo
             for (int k = 0; k < B2X; ++k) {
                 ana_full_df(a1[0][2 * k], a1[0][2 * k + 1], a1[1][2 * k], a1[1][2 * k + 1], a2[k], hl2[k],
                             lh2[k], hh2[k]);
-                hl2[k] = shrink_value(hl2[k], mode, t2);
-                lh2[k] = shrink_value(lh2[k], mode, t2);
-                hh2[k] = shrink_value(hh2[k], mode, t2);
+                hl2[k] = detail_op<OP>(hl2[k], mode, t2, acc);
+                lh2[k] = detail_op<OP>(lh2[k], mode, t2, acc);
+                hh2[k] = detail_op<OP>(hh2[k], mode, t2, acc);
                 ll2[k] = df_round(a2[k]);
+                if (L == 2) ll_op<OP>(ll2[k], acc);
             }
             if (L >= 3) {
                 // ---- levels 3..L on the LL2 region, by the first wavefront
@@ -370,9 +429,9 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_full_kernel(const void* x, vo
                             float hl, lh, hh;
                             ana_full_f(x00, x01, x10, x11, ll, hl, lh, hh);
                             nxt[q] = df_round(ll);
-                            dets[off + q] = shrink_value(hl, mode, tl);
-                            dets[off + nb + q] = shrink_value(lh, mode, tl);
-                            dets[off + 2 * nb + q] = shrink_value(hh, mode, tl);
+                            dets[off + q] = detail_op<OP>(hl, mode, tl, acc);
+                            dets[off + nb + q] = detail_op<OP>(lh, mode, tl, acc);
+                            dets[off + 2 * nb + q] = detail_op<OP>(hh, mode, tl, acc);
                         }
                         off += 3 * nb;
                         ch = bh;
@@ -384,6 +443,8 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_full_kernel(const void* x, vo
                         __builtin_amdgcn_wave_barrier();
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     }
+                    if constexpr (OP == kOpL1)                   // LL_L (ch x cw) joins the loss
+                        for (int q = t; q < ch * cw; q += 64) ll_op<OP>(cur[q], acc);
                     for (int lev = L; lev >= 3; --lev) {          // synthesis
                         const int bh = ch, bw = cw, nb = bh * bw, ow = 2 * bw;
                         const int o = doff[lev];
@@ -428,7 +489,28 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_full_kernel(const void* x, vo
                          v[2 * i][2 * k + 1], v[2 * i + 1][2 * k], v[2 * i + 1][2 * k + 1]);
 #pragma unroll
         for (int i = 0; i < RY; ++i) st_vec<S, RX>(dst + (int64_t)(lr0 + i) * w + lc0, v[i]);
+        if constexpr (OP == kOpL1) tile_loss<GY * GX>(acc, sh.partial, b);
         if (L >= 3) __syncthreads();         // LDS reuse by the next tile
+    }
+}
+
+// Loss of each item: its interior tiles' partials [item * per_full, ...) and
+// its edge tiles' partials [nfull + item * per_edge, ...), summed in a fixed
+// order by one work-group per item.
+__global__ __launch_bounds__(256) void l1_loss_reduce_kernel(const double* partial, double* loss,
+                                                            int64_t batch, int64_t per_full,
+                                                            int64_t per_edge, int64_t nfull) {
+    __shared__ double red[4];
+    for (int64_t item = blockIdx.x; item < batch; item += gridDim.x) {
+        double v = 0.0;
+        for (int64_t i = threadIdx.x; i < per_full; i += 256) v += partial[item * per_full + i];
+        for (int64_t i = threadIdx.x; i < per_edge; i += 256) v += partial[nfull + item * per_edge + i];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) loss[item] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
     }
 }
 
@@ -465,26 +547,44 @@ static hipError_t launch_shrink1d(const void* x, void* y, int64_t n, int L, int6
     return hipSuccess;
 }
 
+// Tile grid of the 2D pipeline: interior tiles, then the right column and
+// the bottom row of partial tiles.
+struct ShrinkGrid2D {
+    int64_t full_x, full_y, right, bottom;
+    int64_t per_full() const { return full_x * full_y; }
+    int64_t per_edge() const { return right + bottom; }
+};
+
 template <class S>
+static ShrinkGrid2D shrink_grid2d(int64_t h, int64_t w) {
+    constexpr int TH = 32, TW = 32 * (16 / S::kBytes);
+    ShrinkGrid2D g;
+    const int64_t tiles_x = (w + TW - 1) / TW, tiles_y = (h + TH - 1) / TH;
+    g.full_x = w / TW;
+    g.full_y = h / TH;
+    g.right = tiles_x > g.full_x ? g.full_y : 0;
+    g.bottom = tiles_y > g.full_y ? tiles_x : 0;
+    return g;
+}
+
+template <class S, int OP>
 static hipError_t launch_shrink2d(const void* x, void* y, int64_t h, int64_t w, int L, int64_t batch,
                                   const ShrinkArgs& a, hipStream_t s) {
-    constexpr int GY = 8, GX = 32, TH = 4 * GY, TW = GX * (16 / S::kBytes);
-    const int64_t tiles_x = (w + TW - 1) / TW, tiles_y = (h + TH - 1) / TH;
-    const int64_t full_x = w / TW, full_y = h / TH;
-    const int64_t interior = full_x * full_y * batch;
+    constexpr int GY = 8, GX = 32;
+    const ShrinkGrid2D g = shrink_grid2d<S>(h, w);
+    const int64_t interior = g.per_full() * batch;
     if (interior > 0) {
         const unsigned grid = (unsigned)(interior < kMaxGridShrink ? interior : kMaxGridShrink);
-        hipLaunchKernelGGL((shrink2d_full_kernel<S, GY, GX>), dim3(grid), dim3(GY * GX), 0, s, x, y, h, w,
-                           L, full_x, full_y, interior, a);
+        hipLaunchKernelGGL((shrink2d_full_kernel<S, GY, GX, OP>), dim3(grid), dim3(GY * GX), 0, s, x, y, h,
+                           w, L, g.full_x, g.full_y, interior, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int64_t right = tiles_x > full_x ? full_y : 0, bottom = tiles_y > full_y ? tiles_x : 0;
-    const int64_t edge = (right + bottom) * batch;
+    const int64_t edge = g.per_edge() * batch;
     if (edge > 0) {
         const unsigned grid = (unsigned)(edge < kMaxGridShrink ? edge : kMaxGridShrink);
-        hipLaunchKernelGGL((shrink2d_edge_kernel<S, GY, GX>), dim3(grid), dim3(GY * GX), 0, s, x, y, h, w,
-                           L, full_x, full_y, right, bottom, edge, a);
+        hipLaunchKernelGGL((shrink2d_edge_kernel<S, GY, GX, OP>), dim3(grid), dim3(GY * GX), 0, s, x, y, h,
+                           w, L, g.full_x, g.full_y, g.right, g.bottom, edge, a, interior);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -507,11 +607,40 @@ int run_shrink_2d(const void* in, void* out, int64_t h, int64_t w, int L, int64_
     const ShrinkArgs a = shrink_args(L, mode, thr);
     hipError_t e;
     switch (dtype) {
-        case 0: e = launch_shrink2d<StF32>(in, out, h, w, L, batch, a, s); break;
-        case 1: e = launch_shrink2d<StBF16>(in, out, h, w, L, batch, a, s); break;
-        default: e = launch_shrink2d<StF16>(in, out, h, w, L, batch, a, s); break;
+        case 0: e = launch_shrink2d<StF32, kOpShrink>(in, out, h, w, L, batch, a, s); break;
+        case 1: e = launch_shrink2d<StBF16, kOpShrink>(in, out, h, w, L, batch, a, s); break;
+        default: e = launch_shrink2d<StF16, kOpShrink>(in, out, h, w, L, batch, a, s); break;
     }
     return e == hipSuccess ? 0 : hip_error(e, "shrink2d launch");
+}
+
+template <class S>
+static int l1_grad_2d_s(const void* in, void* out, double* loss, int64_t h, int64_t w, int L, int64_t batch,
+                        hipStream_t s) {
+    const ShrinkGrid2D g = shrink_grid2d<S>(h, w);
+    const int64_t nfull = g.per_full() * batch, nparts = nfull + g.per_edge() * batch;
+    ShrinkArgs a{};
+    hipError_t e = hipMallocAsync((void**)&a.partial, (size_t)nparts * sizeof(double), s);
+    if (e != hipSuccess) return hip_error(e, "hipMallocAsync (loss partials)");
+    e = launch_shrink2d<S, kOpL1>(in, out, h, w, L, batch, a, s);
+    if (e == hipSuccess) {
+        const unsigned grid = (unsigned)(batch < kMaxGridShrink ? batch : kMaxGridShrink);
+        hipLaunchKernelGGL(l1_loss_reduce_kernel, dim3(grid), dim3(256), 0, s, a.partial, loss, batch,
+                           g.per_full(), g.per_edge(), nfull);
+        e = hipGetLastError();
+    }
+    const hipError_t ef = hipFreeAsync(a.partial, s);
+    if (e != hipSuccess) return hip_error(e, "l1 gradient launch");
+    return ef == hipSuccess ? 0 : hip_error(ef, "hipFreeAsync");
+}
+
+int run_l1_grad_2d(const void* in, void* out, double* loss, int64_t h, int64_t w, int L, int64_t batch,
+                   int dtype, hipStream_t s) {
+    switch (dtype) {
+        case 0: return l1_grad_2d_s<StF32>(in, out, loss, h, w, L, batch, s);
+        case 1: return l1_grad_2d_s<StBF16>(in, out, loss, h, w, L, batch, s);
+        default: return l1_grad_2d_s<StF16>(in, out, loss, h, w, L, batch, s);
+    }
 }
 
 }  // namespace haar

@@ -119,6 +119,20 @@ def inv3d(y: torch.Tensor, levels: int, out: torch.Tensor | None = None) -> torc
     return x
 
 
+def l1_grad2d(x: torch.Tensor, levels: int, out: torch.Tensor | None = None):
+    """One fused pass: the loss sum |details| + 0.5 ||LL_L||^2 of the 2D
+    analysis of each item of x and its gradient with respect to x.
+    Returns (loss, grad): loss is a float64 tensor of the batch shape."""
+    x = _prep(x, 2)
+    g = _out(x, out)
+    h, w = x.shape[-2], x.shape[-1]
+    batch = x.numel() // (h * w) if h * w > 0 else 0
+    loss = torch.empty(x.shape[:-2], dtype=torch.float64, device=x.device)
+    _abi.check(_abi.haar_l1_grad_2d(x.data_ptr(), g.data_ptr(), loss.data_ptr() if batch else 0, h, w,
+                                    int(levels), batch, dtype_code(x), _stream(x.device)))
+    return loss, g
+
+
 SHRINK_MODES = {"hard": 0, "soft": 1}
 
 

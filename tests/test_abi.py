@@ -92,6 +92,10 @@ X, Y = 0x10000000, 0x20000000     # fake, non-overlapping device addresses (neve
     (lambda a: a.haar_inv_3d(X, X + 64, 8, 8, 8, 1, 1, 0, 0), 5),                   # overlap
     (lambda a: a.haar_fwd_3d(X, Y, 1 << 30, 1 << 30, 1 << 30, 1, 1, 0, 0), 3),      # size overflow
     (lambda a: a.haar_fwd_3d(0, Y, 8, 8, 8, 1, 1, 0, 0), 1),                        # NULL input
+    (lambda a: a.haar_l1_grad_2d(X, Y, 0x30000000, 64, 64, 6, 1, 0, 0), 9),         # beyond one tile
+    (lambda a: a.haar_l1_grad_2d(X, Y, 0x30000000, 8, 8, 4, 1, 0, 0), 4),           # levels > log2
+    (lambda a: a.haar_l1_grad_2d(X, Y, 0, 64, 64, 2, 1, 0, 0), 1),                  # no loss array
+    (lambda a: a.haar_l1_grad_2d(X, X + 8, 0x30000000, 64, 64, 2, 1, 0, 0), 5),     # overlap
 ])
 def test_validation_codes(abi, call, code):
     assert call(abi) == code
