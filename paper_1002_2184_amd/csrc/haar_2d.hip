@@ -122,7 +122,8 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D
 // Index -> (GY, GX, XCD remap, work-groups per CU, analysis thread map);
 // RY = 4 and RX = 16 bytes / element size.  Work-groups per CU = 0: one tile
 // per work-group; k > 0: a persistent interior grid of k work-groups per
-// compute unit.  Map 1: wavefront-local analysis (see thread_rc).
+// compute unit.  Map 1: wavefront-local analysis; map 2: two-row
+// wavefronts (see thread_rc).
 #define HAAR_2D_TILES(X)      \
     X(0, 8, 32, 0, 0, 0)      \
     X(1, 8, 64, 0, 0, 0)      \
@@ -137,9 +138,10 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D
     X(10, 8, 16, 0, 0, 1)     \
     X(11, 8, 8, 0, 0, 1)      \
     X(12, 8, 16, 1, 0, 1)     \
-    X(13, 8, 8, 1, 0, 1)
+    X(13, 8, 8, 1, 0, 1)      \
+    X(14, 8, 64, 0, 0, 2)
 
-int num_tile_configs_2d(int) { return 14; }
+int num_tile_configs_2d(int) { return 15; }
 
 Tile2D tile_config_2d(int elem_bytes, int index) {
     const int rx = 16 / elem_bytes;

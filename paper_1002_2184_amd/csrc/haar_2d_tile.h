@@ -126,6 +126,15 @@ __device__ __forceinline__ void thread_rc(int t, int& rg, int& cg) {
     if constexpr (MAP == 0) {
         rg = t / GX;
         cg = t % GX;
+    } else if constexpr (MAP == 2) {
+        // two-row wavefronts: wavefront w holds row groups 2 (w / 2) and
+        // 2 (w / 2) + 1 (lanes 0-31 and 32-63) of column groups
+        // 32 (w % 2) .. + 31, so each 2x2 block of LL2 lies in one wavefront
+        // while every load and level-1/2 store still covers whole lines
+        static_assert(GY == 8 && GX == 64, "two-row wavefronts are defined for 8 x 64 groups");
+        const int lane = t & 63, w = t >> 6;
+        rg = 2 * (w >> 1) + (lane >> 5);
+        cg = 32 * (w & 1) + (lane & 31);
     } else {
         static_assert(GY == 8 && GX % 8 == 0, "wavefront-local tiles are 8 x 8k groups");
         const int lane = t & 63;
@@ -371,11 +380,13 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
     float* Blo = Bhi + G::BN;
     int rh = (th + 3) >> 2, rw = (tw + 3) >> 2;   // local region size at level 2
     int first = 3;                                // first level of the single-wave phase
-    if constexpr (FULL && GX == 32 && MAP == 0) {
-        // Level 3 inside each wavefront: with 32 column groups a wave holds
-        // LL2 rows 2w (lanes 0-31) and 2w+1 (lanes 32-63), so every 2x2 block
-        // of LL2 lies in one wave: xor-shuffles fetch the partners.
-        const int lane = t & 63, w = t >> 6;
+    if constexpr (FULL && ((GX == 32 && MAP == 0) || MAP == 2)) {
+        // Level 3 inside each wavefront: a wave holds LL2 rows 2q (lanes
+        // 0-31) and 2q+1 (lanes 32-63) of 32 column groups (q = w with 32
+        // column groups, w / 2 with the two-row map), so every 2x2 block of
+        // LL2 lies in one wave: xor-shuffles fetch the partners.
+        const int lane = t & 63, w = MAP == 2 ? (t >> 7) : (t >> 6);
+        const int cb3 = MAP == 2 ? ((t >> 6) & 1) * 16 * B2X : 0;   // first LL3 column of the wave
         df x00, x01, x10, x11;
         if constexpr (B2X == 1) {
             const df a = a2[0][0];
@@ -396,15 +407,23 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
             float hl, lh, hh;
             ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
             const int64_t hs = ceil_shift(p.h, 3), ws = ceil_shift(p.w, 3);
-            const int64_t R = (r0 >> 3) + w, C = (c0 >> 3) + k;
-            st1<SD>(det + R * dp + ws + C, hl);
-            st1<SD>(det + (hs + R) * dp + C, lh);
-            st1<SD>(det + (hs + R) * dp + ws + C, hh);
+            const int64_t R = (r0 >> 3) + w, C = (c0 >> 3) + cb3 + k;
+            if constexpr (MAP == 2) {
+                // half lines (the other half comes from the neighbouring
+                // wavefront of the same work-group): merged in L2
+                st1_cached<SD>(det + R * dp + ws + C, hl);
+                st1_cached<SD>(det + (hs + R) * dp + C, lh);
+                st1_cached<SD>(det + (hs + R) * dp + ws + C, hh);
+            } else {
+                st1<SD>(det + R * dp + ws + C, hl);
+                st1<SD>(det + (hs + R) * dp + C, lh);
+                st1<SD>(det + (hs + R) * dp + ws + C, hh);
+            }
             if (L == 3) {
                 st1<SL>(llp + R * lp + C, df_round(ll));
             } else {
-                Bhi[w * (TW / 8) + k] = ll.hi;
-                Blo[w * (TW / 8) + k] = ll.lo;
+                Bhi[w * (TW / 8) + cb3 + k] = ll.hi;
+                Blo[w * (TW / 8) + cb3 + k] = ll.lo;
             }
         }
         if (L == 3) return;

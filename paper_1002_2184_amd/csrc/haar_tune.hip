@@ -52,9 +52,12 @@ int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels, 
     if (fallback >= 0) return fallback;
     // measured defaults (4096^2, 5 levels, cold HBM): FP32, 32 x 256 tiles
     // (4 x 4 registers per thread, 512 threads), one tile per work-group,
-    // blocks dealt round-robin to the XCDs; 16-bit analysis, the 256-thread
-    // 32 x 256 tiles (19.2 us against 22.0 us for 32 x 512)
-    return (dtype != 0 && !inverse) ? 0 : 1;
+    // blocks dealt round-robin to the XCDs, the analysis with two-row
+    // wavefronts (26.6-27.0 us against 27.1-27.7 us, level 3 by shuffles);
+    // 16-bit analysis, the 256-thread 32 x 256 tiles (16.1-16.4 us against
+    // 18.0 us for 32 x 512)
+    if (dtype == 0) return inverse ? 1 : 14;
+    return inverse ? 1 : 0;
 }
 
 int choose_config_1d(int dtype, bool inverse, int64_t n, int levels) {
@@ -132,7 +135,7 @@ const char* haar_tune_candidate_name(int32_t dtype, int32_t index) {
     if (t.wg_per_cu > 0) snprintf(pers, sizeof pers, ", persistent %d/CU", t.wg_per_cu);
     snprintf(buf, sizeof buf, "tile %dx%d, %d threads, %dx%d per thread%s%s%s", t.th(), t.tw(),
              t.threads(), t.ry, t.rx, t.remap ? ", XCD-contiguous" : "", pers,
-             t.map ? ", wavefront-local analysis" : "");
+             t.map == 1 ? ", wavefront-local analysis" : (t.map == 2 ? ", two-row wavefronts" : ""));
     return buf;
 }
 
