@@ -56,6 +56,28 @@ class HaarInv2D(torch.autograd.Function):
         return T.fwd2d(g.contiguous(), ctx.levels), None
 
 
+class HaarFwd3D(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, levels):
+        ctx.levels = int(levels)
+        return T.fwd3d(x, levels)
+
+    @staticmethod
+    def backward(ctx, g):
+        return T.inv3d(g.contiguous(), ctx.levels), None
+
+
+class HaarInv3D(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y, levels):
+        ctx.levels = int(levels)
+        return T.inv3d(y, levels)
+
+    @staticmethod
+    def backward(ctx, g):
+        return T.fwd3d(g.contiguous(), ctx.levels), None
+
+
 def haar_fwd1d(x, levels):
     return HaarFwd1D.apply(x, levels)
 
@@ -70,3 +92,11 @@ def haar_fwd2d(x, levels):
 
 def haar_inv2d(y, levels):
     return HaarInv2D.apply(y, levels)
+
+
+def haar_fwd3d(x, levels):
+    return HaarFwd3D.apply(x, levels)
+
+
+def haar_inv3d(y, levels):
+    return HaarInv3D.apply(y, levels)

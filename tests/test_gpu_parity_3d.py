@@ -132,3 +132,48 @@ def test_constant_volume_exact(T):
         m = np.ones((16, 32, 128), bool)
         m[:dL, :hL, :wL] = False
         assert np.all(y[:, m] == 0.0)
+
+
+@pytest.mark.parametrize("dt", [G.F32, G.BF16])
+def test_full_size_phantom_volumes(T, dt):
+    """The suite's workload size: 4 x 256^3 phantom volumes, 3 levels (one
+    fused pass), every coefficient against the oracle; then L8 (three
+    passes) on one volume."""
+    import torch
+    rng = np.random.default_rng(8)
+    base = G.phantom_volume(rng, 256, 256, 256)
+    x64 = np.stack([base + rng.normal(0.0, 0.02, base.shape) for _ in range(4)])
+    xs = G.to_storage(x64, dt)
+    del x64
+    xw = G.widen(xs, dt)
+    ref = oracle.fwd_3d(xw, 3)
+    y = T.fwd3d(to_device(xs, dt), 3)
+    _check_fwd(G.widen(to_host(y, dt), dt), ref, xw, dt, 3, f"fwd3d 4x256^3 {G.DTYPE_NAMES[dt]}")
+    x2 = G.widen(to_host(T.inv3d(y, 3), dt), dt)
+    for b in range(4):
+        check_roundtrip(x2[b], xw[b], dt, f"round trip 4x256^3 item {b}")
+    del y, ref, x2
+    torch.cuda.empty_cache()
+    ref8 = oracle.fwd_3d(xw[:1], 8)
+    y8 = T.fwd3d(to_device(xs[:1], dt), 8)
+    _check_fwd(G.widen(to_host(y8, dt), dt), ref8, xw[:1], dt, 8, f"fwd3d 256^3 L8 {G.DTYPE_NAMES[dt]}")
+
+
+def test_autograd_3d_adjoint(T):
+    """Backward of the 3D analysis is the oracle's transpose W^T g (the
+    synthesis), and backward of the synthesis is the analysis: checked on an
+    odd volume through torch.autograd with the oracle's adjoint."""
+    import torch
+    from paper_1002_2184_amd import autograd as AG
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, 9, 20, 70))
+    g = rng.standard_normal((2, 9, 20, 70))
+    L = 4
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda", requires_grad=True)
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda")
+    (gx,) = torch.autograd.grad(AG.HaarFwd3D.apply(xt, L), xt, gt)
+    want = oracle.inv_3d(g.astype(np.float32).astype(np.float64), L)
+    check_signal(gx.cpu().numpy().astype(np.float64), want, rms(g), G.F32, "HaarFwd3D backward")
+    (gy,) = torch.autograd.grad(AG.HaarInv3D.apply(xt, L), xt, gt)
+    want = oracle.fwd_3d(g.astype(np.float32).astype(np.float64), L)
+    check_coeffs_f32(gy.cpu().numpy().astype(np.float64), want, rms(g), "HaarInv3D backward")
