@@ -245,15 +245,28 @@ def test_config5_sample_per_band(P):
     zd = [torch.empty_like(g) for g in gd]
     P.Plan2D(gd, zd, 4, inverse=True).execute()
     torch.cuda.synchronize()
+    per_level = {}       # level (0 = LL_4) -> worst (max err / band peak, RMS err / band RMS)
+    bwd_worst = 0.0
     for x, y, g, z, s in zip(imgs, yd, grads, zd, shapes):
         xw = G.widen(x, G.BF16)
         ref = oracle.fwd_2d(xw, 4)
-        check_lowp_coeffs(G.widen(to_host(y, G.BF16), G.BF16), ref, rms(xw), G.BF16,
-                          band_views(tuple(s), 4), f"config5 fwd {s}", band_gate=True)
+        table = check_lowp_coeffs(G.widen(to_host(y, G.BF16), G.BF16), ref, rms(xw), G.BF16,
+                                  band_views(tuple(s), 4), f"config5 fwd {s}", band_gate=True)
+        for key, v in table.items():
+            lev = 0 if key == "LL" else key[1]
+            a, b = per_level.get(lev, (0.0, 0.0))
+            per_level[lev] = (max(a, v["max_err_over_band_peak"]), max(b, v["rms_err_over_band_rms"]))
         gw = G.widen(g, G.BF16)
         gref = oracle.inv_2d(gw, 4)
         zw = G.widen(to_host(z, G.BF16), G.BF16)
-        check_lowp_signal(zw, gref, rms(gw), G.BF16, f"config5 bwd {s}")
+        bwd_worst = max(bwd_worst, check_lowp_signal(zw, gref, rms(gw), G.BF16, f"config5 bwd {s}"))
+    # the per-level error report of the BF16 batch (worst over the sample)
+    print("\nBF16 batch, error of the stored coefficients against the FP64 oracle, worst of 24 images:")
+    for lev in sorted(per_level):
+        a, b = per_level[lev]
+        name = "LL_4" if lev == 0 else f"level {lev} (HL, LH, HH)"
+        print(f"  {name:>22}: max err / max|band| {a:.2e}, RMS err / RMS band {b:.2e}")
+    print(f"  backward (synthesis of the BF16 gradient): max err / RMS(g) {bwd_worst:.2e}")
         # images are U[0, 1]: the literal max-abs signal gate also holds for a
         # round trip of the image itself
     rt = [torch.empty_like(y) for y in yd]
