@@ -236,11 +236,12 @@ int haar_max_levels_3d(int64_t depth, int64_t height, int64_t width);
  *
  * A plan lists the work units of all items (2D: tiles, 1D: chunks of 4096
  * samples), largest items first, and haar_plan_execute() enqueues ONE
- * persistent kernel (grid = resident work-groups of the device) that drains
- * the list.  1D plans default to a strided walk (work-group b takes units
- * b, b + G, b + 2G, ...: the chunks are uniform); 2D plans default to
- * claiming units with an atomic counter (edge tiles differ in cost).  See
- * haar_plan_set_config.  A 1D analysis plan with items deeper than 12
+ * kernel that drains the list, under one of three schedules: a persistent
+ * grid (the resident work-groups of the device) walking the list with a
+ * stride, a persistent grid claiming units from an atomic counter, or one
+ * work-group per unit.  Defaults, as measured: 2D analysis plans claim
+ * their tiles (edge tiles differ in cost); 2D synthesis plans and all 1D
+ * plans run one unit per work-group.  See haar_plan_set_config.  A 1D analysis plan with items deeper than 12
  * levels enqueues a second, small kernel that finishes those items, one
  * work-group per item.  The plan itself holds host memory only; the
  * device-side tables and counters live in a caller-owned workspace of
@@ -286,15 +287,15 @@ int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype,
 int haar_plan_workspace_size(const haar_plan* plan, size_t* bytes);
 int haar_plan_upload(haar_plan* plan, void* workspace, void* stream);
 int haar_plan_execute(const haar_plan* plan, void* workspace, void* stream);
-/* Number of work units and the persistent grid size (work-groups). */
+/* Number of work units and the grid size (work-groups) of one execute. */
 int haar_plan_info(const haar_plan* plan, int64_t* tiles, int32_t* grid);
 /* Select a plan configuration; the plan must be uploaded again.  The
- * schedule is 0: work-group b runs units b, b + G, b + 2G, ... of the list
- * (1D default), or 1: work-groups claim units from an atomic counter (2D
- * default).
+ * schedule is 0: a persistent grid of G work-groups, work-group b runs units
+ * b, b + G, b + 2G, ... of the list; 1: a persistent grid whose work-groups
+ * claim units from an atomic counter; 2: one work-group per unit.
  * 2D: config = tile shape + 2 * schedule, tile shape 0: 32 rows x 16
- * vectors, 1: 32 rows x 32 vectors (configs 0..3).  1D: config = schedule
- * (0, 1). */
+ * vectors, 1: 32 rows x 32 vectors (configs 0..5).  1D: config = schedule
+ * (0..2). */
 int haar_plan_set_config(haar_plan* plan, int32_t config);
 /* Autotune a plan: time executes of every configuration on `stream`
  * (hipEvents; synchronises the stream; overwrites the items' outputs), keep

@@ -201,9 +201,9 @@ def test_plan_validation_and_sizes(abi, monkeypatch):
     # 32x256 f32 tiles: 64x96 -> 2x1, 33x300 -> 2x2
     assert tiles.value == 6
     assert abi.haar_plan_execute(plan, X, 0) == 8          # not uploaded
-    assert abi.haar_plan_set_config(plan, 4) == 9           # configs 0..3 (shape + 2 * schedule)
+    assert abi.haar_plan_set_config(plan, 6) == 9           # configs 0..5 (shape + 2 * schedule)
     assert abi.haar_plan_set_config(plan, -1) == 9
-    assert abi.haar_plan_set_config(plan, 3) == 0
+    assert abi.haar_plan_set_config(plan, 5) == 0
     monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")
     assert abi.haar_plan_upload(plan, X, 0) == 7             # stopped before any HIP call
     assert abi.haar_plan_upload(plan, X + 8, 0) == 6         # misaligned workspace
