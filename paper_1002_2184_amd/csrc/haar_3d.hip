@@ -38,7 +38,6 @@ namespace {
 
 constexpr int kTZ = 8, kTY = 8, kTX = 64;       // generic tile
 constexpr int kMaxPassLevels3D = 3;            // log2 of the tile's shortest side
-constexpr int kTile = kTZ * kTY * kTX;         // 4096 samples
 constexpr int kThreads3 = 256;
 constexpr double kRs2d = kRsqrt2;               // b00 = a00 = 1/sqrt2
 constexpr double kC3 = kRsqrt2 * 0.5;           // (1/sqrt2)^3 = 1/(2 sqrt2)
@@ -106,71 +105,15 @@ __device__ __forceinline__ Level3 level_sizes(const Pass3D& p, int j) {
 }
 
 // ---------------------------------------------------------------------------
-// Generic path: the tile in LDS (FP64), one 1D level per axis and level.
+// Generic path (edge tiles, odd counts): one pass per level over the
+// level's 2 x 2 x 2 blocks.  A thread takes whole blocks: it reads the
+// block's (up to) 8 values, runs the three axis butterflies with the carry
+// rule on every axis whose partner is missing, writes the detail octants
+// straight to their packed positions and the LLL value to LDS for the next
+// level (or to its final place after the pass's last level).  Level 1
+// reads the region from memory and the synthesis's level 1 writes it, so
+// only the small LLL regions cross LDS, with one barrier per level.
 // ---------------------------------------------------------------------------
-
-// One analysis (INV = false) or synthesis level along axis A (0 x, 1 y, 2 z)
-// on every line of the local region [0, nz) x [0, ny) x [0, nx) in sm.  The
-// 2048 (line, pair) slots of a full tile are dealt 8 per thread; the values
-// are read into registers, then written back after a barrier.
-template <int A, bool INV>
-__device__ __forceinline__ void lds_level(double* sm, int nz, int ny, int nx) {
-    const int n = A == 0 ? nx : (A == 1 ? ny : nz);
-    const int pairs = n >> 1, na = n - pairs;
-    constexpr int st = A == 0 ? 1 : (A == 1 ? kTX : kTX * kTY);
-    double u[8], v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int i = threadIdx.x + kThreads3 * k;
-        int z, y, x, m;
-        if (A == 0) { m = i & 31; y = (i >> 5) & 7; z = i >> 8; x = 0; }
-        else if (A == 1) { x = i & 63; m = (i >> 6) & 3; z = i >> 8; y = 0; }
-        else { x = i & 63; y = (i >> 6) & 7; m = i >> 9; z = 0; }
-        const bool act = m < na && z < nz && y < ny && x < nx;
-        const int b = (z * kTY + y) * kTX + x;
-        if (act) {
-            if (m < pairs) {
-                if (!INV) {
-                    const double x0 = sm[b + 2 * m * st], x1 = sm[b + (2 * m + 1) * st];
-                    u[k] = (x0 + x1) * kRs2d;                 // Eq. (11)
-                    v[k] = (x1 - x0) * kRs2d;                 // Eq. (12)
-                } else {
-                    const double a = sm[b + m * st], d = sm[b + (na + m) * st];
-                    u[k] = (a - d) * kRs2d;                   // Eq. (19), even phase
-                    v[k] = (a + d) * kRs2d;                   // odd phase
-                }
-            } else {
-                u[k] = INV ? sm[b + (na - 1) * st] : sm[b + (n - 1) * st];   // carry
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int i = threadIdx.x + kThreads3 * k;
-        int z, y, x, m;
-        if (A == 0) { m = i & 31; y = (i >> 5) & 7; z = i >> 8; x = 0; }
-        else if (A == 1) { x = i & 63; m = (i >> 6) & 3; z = i >> 8; y = 0; }
-        else { x = i & 63; y = (i >> 6) & 7; m = i >> 9; z = 0; }
-        const bool act = m < na && z < nz && y < ny && x < nx;
-        const int b = (z * kTY + y) * kTX + x;
-        if (act) {
-            if (m < pairs) {
-                if (!INV) {
-                    sm[b + m * st] = u[k];
-                    sm[b + (na + m) * st] = v[k];
-                } else {
-                    sm[b + 2 * m * st] = u[k];
-                    sm[b + (2 * m + 1) * st] = v[k];
-                }
-            } else {
-                if (!INV) sm[b + m * st] = u[k];
-                else sm[b + (n - 1) * st] = u[k];
-            }
-        }
-    }
-    __syncthreads();
-}
 
 // Local sample counts of a tile: the tile holds c samples of the region on
 // an axis, hence ceil(c / 2^j) samples of the level-j LLL region (tile
@@ -187,121 +130,160 @@ __device__ __forceinline__ Counts3 tile_counts(const Pass3D& p, int64_t oz, int6
             (int)min<int64_t>(kTX, p.w - ox)};
 }
 
-// Global position in the packed volume of local element (z, y, x) of the
-// level-j octants of a tile at origin (oz, oy, ox): low half at o/2^j + l,
-// high half at {D,H,W}_j + o/2^j + (l - a).
-__device__ __forceinline__ int64_t band_pos(int l, int a, int64_t o, int j, int64_t N) {
-    return l < a ? (o >> j) + l : N + (o >> j) + (l - a);
-}
-
-// The 4096 positions of a tile, 16 per thread, x fastest.  Loops over them
-// are unrolled so that a thread's global loads are all in flight before the
-// first use (one HBM latency per phase instead of one per element).
-constexpr int kPerThread3 = kTile / kThreads3;
-
-struct TilePos {
-    int i, z, y, x;
+// Block grid of level j in a tile: (4 x 4 x 32) >> (j - 1) slots; slot s ->
+// (bz, by, bx) with bx fastest.  LDS holds the LLL region of each level in
+// the same dense layout (pitches YB * XB and XB).
+struct Blocks3 {
+    int xs, ys;                                // log2 of the slot grid's x and y extent
+    __device__ __forceinline__ explicit Blocks3(int j) : xs(6 - j), ys(3 - j) {}
+    __device__ __forceinline__ int n() const { return 1 << (xs + ys + ys); }
+    __device__ __forceinline__ int bx(int s) const { return s & ((1 << xs) - 1); }
+    __device__ __forceinline__ int by(int s) const { return (s >> xs) & ((1 << ys) - 1); }
+    __device__ __forceinline__ int bz(int s) const { return s >> (xs + ys); }
+    __device__ __forceinline__ int at(int z, int y, int x) const { return (z << (xs + ys)) + (y << xs) + x; }
 };
+constexpr int kLll1 = 4 * 4 * 32, kLll2 = 2 * 2 * 16;   // LLL regions of levels 1 and 2 in LDS
+constexpr int kSlots1 = kLll1 / kThreads3;              // level-1 blocks per thread
 
-__device__ __forceinline__ TilePos tile_pos(int k) {
-    const int i = threadIdx.x + kThreads3 * k;
-    return {i, i >> 9, (i >> 6) & 7, i & 63};
-}
-
-// Detail octants of level j between LDS and the packed volume.
-template <class S, bool LOAD>
-__device__ __forceinline__ void lds_details(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
-                                            int64_t ox, const Counts3& c, int j, double* sm) {
-    const Level3 L = level_sizes(p, j);
-    const int nz = c.cz(j - 1), ny = c.cy(j - 1), nx = c.cx(j - 1);
-    const int az = c.cz(j), ay = c.cy(j), ax = c.cx(j);
-    using raw = typename S::raw;
-    raw* det = reinterpret_cast<raw*>(p.det) + item * p.det_b;
-    float r[kPerThread3];
+// Analysis butterflies of one block with the carry rule: along an axis
+// whose partner is missing (flag false) the value passes unscaled and that
+// axis has no detail.  Index dx | dy << 1 | dz << 2; entries of missing
+// samples are never used.
+__device__ __forceinline__ void block_fwd(double* q, bool fx, bool fy, bool fz) {
+    const bool f[3] = {fx, fy, fz};
 #pragma unroll
-    for (int k = 0; k < kPerThread3; ++k) {
-        const TilePos t = tile_pos(k);
-        const bool in = t.z < nz && t.y < ny && t.x < nx && !(t.z < az && t.y < ay && t.x < ax);
-        if (!in) continue;
-        const int64_t g = band_pos(t.z, az, oz, j, L.D) * p.det_p + band_pos(t.y, ay, oy, j, L.H) * p.det_r +
-                          band_pos(t.x, ax, ox, j, L.W);
-        if (LOAD)
-            r[k] = ld1<S>(det + g);
-        else
-            st1_cached<S>(det + g, (float)sm[t.i]);
-    }
-    if (LOAD) {
+    for (int a = 0; a < 3; ++a) {
+        const int bit = 1 << a;
+        if (!f[a]) continue;
 #pragma unroll
-        for (int k = 0; k < kPerThread3; ++k) {
-            const TilePos t = tile_pos(k);
-            if (t.z < nz && t.y < ny && t.x < nx && !(t.z < az && t.y < ay && t.x < ax))
-                sm[t.i] = (double)r[k];
-        }
+        for (int i = 0; i < 8; ++i)
+            if (!(i & bit)) {
+                const double x0 = q[i], x1 = q[i | bit];
+                q[i] = (x0 + x1) * kRs2d;              // Eq. (11)
+                q[i | bit] = (x1 - x0) * kRs2d;        // Eq. (12)
+            }
     }
 }
 
-// Tile box [0, bz) x [0, by) x [0, bx) from a buffer (origin b, plane and row
-// strides) into LDS.
-template <class S, bool DF>
-__device__ __forceinline__ void lds_fill(double* sm, const void* src, int64_t b, int64_t sp, int64_t sr, int bz,
-                                         int by, int bx) {
-    double r[kPerThread3];
+// Synthesis of one block (Eq. (19) per complete axis; carry otherwise).
+__device__ __forceinline__ void block_inv(double* q, bool fx, bool fy, bool fz) {
+    const bool f[3] = {fx, fy, fz};
 #pragma unroll
-    for (int k = 0; k < kPerThread3; ++k) {
-        const TilePos t = tile_pos(k);
-        if (t.z < bz && t.y < by && t.x < bx) r[k] = ld_val<S, DF>(src, b + t.z * sp + t.y * sr + t.x);
-    }
+    for (int a = 2; a >= 0; --a) {
+        const int bit = 1 << a;
+        if (!f[a]) continue;
 #pragma unroll
-    for (int k = 0; k < kPerThread3; ++k) {
-        const TilePos t = tile_pos(k);
-        if (t.z < bz && t.y < by && t.x < bx) sm[t.i] = r[k];
+        for (int i = 0; i < 8; ++i)
+            if (!(i & bit)) {
+                const double lo = q[i], hi = q[i | bit];
+                q[i] = (lo - hi) * kRs2d;              // even phase
+                q[i | bit] = (lo + hi) * kRs2d;        // odd phase
+            }
     }
 }
 
-template <class S, bool DF>
-__device__ __forceinline__ void lds_drain(const double* sm, void* dst, int64_t b, int64_t sp, int64_t sr, int bz,
-                                          int by, int bx) {
-#pragma unroll
-    for (int k = 0; k < kPerThread3; ++k) {
-        const TilePos t = tile_pos(k);
-        if (t.z < bz && t.y < by && t.x < bx) st_val<S, DF>(dst, b + t.z * sp + t.y * sr + t.x, sm[t.i]);
-    }
+// Packed position of code c of the level-j block (bz, by, bx) in a tile at
+// (oz, oy, ox): the low half of an axis at o / 2^j + b, the high half at
+// N_j + o / 2^j + b.
+__device__ __forceinline__ int64_t octant_pos(const Pass3D& p, const Level3& Lj, int j, int c, int64_t oz,
+                                              int64_t oy, int64_t ox, int bz, int by, int bx) {
+    const int64_t gz = ((c & 4) ? Lj.D : 0) + (oz >> j) + bz;
+    const int64_t gy = ((c & 2) ? Lj.H : 0) + (oy >> j) + by;
+    const int64_t gx = ((c & 1) ? Lj.W : 0) + (ox >> j) + bx;
+    return gz * p.det_p + gy * p.det_r + gx;
 }
 
 template <class S, bool SRCDF, bool LLDF>
 __device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, double* sm) {
+    using raw = typename S::raw;
     const Counts3 c = tile_counts(p, oz, oy, ox);
-    lds_fill<S, SRCDF>(sm, p.src, item * p.src_b + oz * p.src_p + oy * p.src_r + ox, p.src_p, p.src_r, c.z,
-                       c.y, c.x);
-    __syncthreads();
-    for (int j = 1; j <= p.levels; ++j) {
-        const int nz = c.cz(j - 1), ny = c.cy(j - 1), nx = c.cx(j - 1);
-        lds_level<0, false>(sm, nz, ny, nx);
-        lds_level<1, false>(sm, nz, ny, nx);
-        lds_level<2, false>(sm, nz, ny, nx);
-        lds_details<S, false>(p, item, oz, oy, ox, c, j, sm);
-    }
     const int J = p.levels;
-    lds_drain<S, LLDF>(sm, p.ll, item * p.ll_b + (oz >> J) * p.ll_p + (oy >> J) * p.ll_r + (ox >> J), p.ll_p,
-                       p.ll_r, c.cz(J), c.cy(J), c.cx(J));
+    raw* det = reinterpret_cast<raw*>(p.det) + item * p.det_b;
+    double* lll[2] = {sm, sm + kLll1};         // LLL_1 (4 x 4 x 32), LLL_2 (2 x 2 x 16)
+    for (int j = 1; j <= J; ++j) {
+        const Blocks3 B(j);
+        const Blocks3 P(j - 1 > 0 ? j - 1 : 1);   // layout of the level-(j-1) LLL in LDS
+        const int nz = c.cz(j - 1), ny = c.cy(j - 1), nx = c.cx(j - 1);
+        const int bz_n = c.cz(j), by_n = c.cy(j), bx_n = c.cx(j);
+        const Level3 Lj = level_sizes(p, j);
+#pragma unroll
+        for (int k = 0; k < kSlots1; ++k) {
+            const int s = threadIdx.x + kThreads3 * k;
+            if (s >= B.n()) continue;
+            const int bx = B.bx(s), by = B.by(s), bz = B.bz(s);
+            if (bz >= bz_n || by >= by_n || bx >= bx_n) continue;
+            const bool fx = 2 * bx + 1 < nx, fy = 2 * by + 1 < ny, fz = 2 * bz + 1 < nz;
+            double q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int dx = i & 1, dy = (i >> 1) & 1, dz = i >> 2;
+                q[i] = 0.0;
+                if ((dx && !fx) || (dy && !fy) || (dz && !fz)) continue;
+                const int z = 2 * bz + dz, y = 2 * by + dy, x = 2 * bx + dx;
+                if (j == 1)
+                    q[i] = ld_val<S, SRCDF>(p.src, item * p.src_b + (oz + z) * p.src_p + (oy + y) * p.src_r + ox + x);
+                else
+                    q[i] = lll[j - 2][P.at(z, y, x)];
+            }
+            block_fwd(q, fx, fy, fz);
+#pragma unroll
+            for (int code = 1; code < 8; ++code)
+                if ((!(code & 1) || fx) && (!(code & 2) || fy) && (!(code & 4) || fz))
+                    st1_cached<S>(det + octant_pos(p, Lj, j, code, oz, oy, ox, bz, by, bx), (float)q[code]);
+            if (j == J)
+                st_val<S, LLDF>(p.ll, item * p.ll_b + ((oz >> j) + bz) * p.ll_p + ((oy >> j) + by) * p.ll_r +
+                                          (ox >> j) + bx, q[0]);
+            else
+                lll[j - 1][B.at(bz, by, bx)] = q[0];
+        }
+        if (j < J) __syncthreads();
+    }
 }
 
 template <class S, bool DSTDF, bool LLDF>
 __device__ void inv3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy, int64_t ox, double* sm) {
+    using raw = typename S::raw;
     const Counts3 c = tile_counts(p, oz, oy, ox);
     const int J = p.levels;
-    lds_fill<S, LLDF>(sm, p.ll, item * p.ll_b + (oz >> J) * p.ll_p + (oy >> J) * p.ll_r + (ox >> J), p.ll_p,
-                      p.ll_r, c.cz(J), c.cy(J), c.cx(J));
+    const raw* det = reinterpret_cast<const raw*>(p.det) + item * p.det_b;
+    double* lll[2] = {sm, sm + kLll1};
     for (int j = J; j >= 1; --j) {
-        lds_details<S, true>(p, item, oz, oy, ox, c, j, sm);
-        __syncthreads();
+        const Blocks3 B(j);
+        const Blocks3 P(j - 1 > 0 ? j - 1 : 1);
         const int nz = c.cz(j - 1), ny = c.cy(j - 1), nx = c.cx(j - 1);
-        lds_level<2, true>(sm, nz, ny, nx);
-        lds_level<1, true>(sm, nz, ny, nx);
-        lds_level<0, true>(sm, nz, ny, nx);
+        const int bz_n = c.cz(j), by_n = c.cy(j), bx_n = c.cx(j);
+        const Level3 Lj = level_sizes(p, j);
+#pragma unroll
+        for (int k = 0; k < kSlots1; ++k) {
+            const int s = threadIdx.x + kThreads3 * k;
+            if (s >= B.n()) continue;
+            const int bx = B.bx(s), by = B.by(s), bz = B.bz(s);
+            if (bz >= bz_n || by >= by_n || bx >= bx_n) continue;
+            const bool fx = 2 * bx + 1 < nx, fy = 2 * by + 1 < ny, fz = 2 * bz + 1 < nz;
+            double q[8];
+            q[0] = j == J ? ld_val<S, LLDF>(p.ll, item * p.ll_b + ((oz >> j) + bz) * p.ll_p +
+                                                      ((oy >> j) + by) * p.ll_r + (ox >> j) + bx)
+                          : lll[j - 1][B.at(bz, by, bx)];
+#pragma unroll
+            for (int code = 1; code < 8; ++code) {
+                q[code] = 0.0;
+                if ((!(code & 1) || fx) && (!(code & 2) || fy) && (!(code & 4) || fz))
+                    q[code] = (double)ld1<S>(det + octant_pos(p, Lj, j, code, oz, oy, ox, bz, by, bx));
+            }
+            block_inv(q, fx, fy, fz);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int dx = i & 1, dy = (i >> 1) & 1, dz = i >> 2;
+                if ((dx && !fx) || (dy && !fy) || (dz && !fz)) continue;
+                const int z = 2 * bz + dz, y = 2 * by + dy, x = 2 * bx + dx;
+                if (j == 1)
+                    st_val<S, DSTDF>(p.dst, item * p.dst_b + (oz + z) * p.dst_p + (oy + y) * p.dst_r + ox + x, q[i]);
+                else
+                    lll[j - 2][P.at(z, y, x)] = q[i];
+            }
+        }
+        if (j > 1) __syncthreads();
     }
-    lds_drain<S, DSTDF>(sm, p.dst, item * p.dst_b + oz * p.dst_p + oy * p.dst_r + ox, p.dst_p, p.dst_r, c.z,
-                        c.y, c.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -664,7 +646,7 @@ __global__ __launch_bounds__(kThreads3) void inv3d_full_kernel(Pass3D p) {
 
 template <class S, bool RDF, bool LDF>
 __global__ __launch_bounds__(kThreads3) void fwd3d_edge_kernel(Pass3D p) {
-    __shared__ double sm[kTile];
+    __shared__ double sm[kLll1 + kLll2];
     for (int64_t t = blockIdx.x; t < p.nedge; t += gridDim.x) {
         int64_t item, oz, oy, ox;
         edge_origin(p, t, item, oz, oy, ox);
@@ -675,7 +657,7 @@ __global__ __launch_bounds__(kThreads3) void fwd3d_edge_kernel(Pass3D p) {
 
 template <class S, bool RDF, bool LDF>
 __global__ __launch_bounds__(kThreads3) void inv3d_edge_kernel(Pass3D p) {
-    __shared__ double sm[kTile];
+    __shared__ double sm[kLll1 + kLll2];
     for (int64_t t = blockIdx.x; t < p.nedge; t += gridDim.x) {
         int64_t item, oz, oy, ox;
         edge_origin(p, t, item, oz, oy, ox);
