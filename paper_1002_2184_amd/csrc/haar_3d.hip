@@ -76,6 +76,42 @@ __device__ __forceinline__ void st_val(void* base, int64_t i, double v) {
         st1_cached<S>(reinterpret_cast<typename S::raw*>(base) + i, (float)v);
 }
 
+// Samples i and i + 1 of a row (both when `two`, else i alone): one 8-byte
+// access of storage samples or one 16-byte access of FP64 scratch.
+template <class S, bool DF>
+__device__ __forceinline__ void ld_pair(const void* base, int64_t i, bool two, double& a, double& b) {
+    if (!two) {
+        a = ld_val<S, DF>(base, i);
+        return;
+    }
+    if constexpr (DF) {
+        const double* p = reinterpret_cast<const double*>(base) + i;
+        a = p[0];
+        b = p[1];
+    } else {
+        float f[2];
+        ld_vec<S, 2>(reinterpret_cast<const typename S::raw*>(base) + i, f);
+        a = (double)f[0];
+        b = (double)f[1];
+    }
+}
+
+template <class S, bool DF>
+__device__ __forceinline__ void st_pair(void* base, int64_t i, bool two, double a, double b) {
+    if (!two) {
+        st_val<S, DF>(base, i, a);
+        return;
+    }
+    if constexpr (DF) {
+        double* p = reinterpret_cast<double*>(base) + i;
+        p[0] = a;
+        p[1] = b;
+    } else {
+        const float f[2] = {(float)a, (float)b};
+        st_vec<S, 2>(reinterpret_cast<typename S::raw*>(base) + i, f);
+    }
+}
+
 // Butterflies over the three axes of a 2 x 2 x 2 block, index dx | dy<<1 |
 // dz<<2.  Analysis leaves at index c the unscaled coefficient that is
 // high-pass along the axes whose bit is set in c (pair: (v0 + v1, v1 - v0));
@@ -215,15 +251,18 @@ __device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
             const bool fx = 2 * bx + 1 < nx, fy = 2 * by + 1 < ny, fz = 2 * bz + 1 < nz;
             double q[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int dx = i & 1, dy = (i >> 1) & 1, dz = i >> 2;
-                q[i] = 0.0;
-                if ((dx && !fx) || (dy && !fy) || (dz && !fz)) continue;
-                const int z = 2 * bz + dz, y = 2 * by + dy, x = 2 * bx + dx;
-                if (j == 1)
-                    q[i] = ld_val<S, SRCDF>(p.src, item * p.src_b + (oz + z) * p.src_p + (oy + y) * p.src_r + ox + x);
-                else
-                    q[i] = lll[j - 2][P.at(z, y, x)];
+            for (int r = 0; r < 4; ++r) {          // the block's rows (dy, dz)
+                const int dy = r & 1, dz = r >> 1;
+                q[2 * r] = q[2 * r + 1] = 0.0;
+                if ((dy && !fy) || (dz && !fz)) continue;
+                const int z = 2 * bz + dz, y = 2 * by + dy, x = 2 * bx;
+                if (j == 1) {
+                    const int64_t g = item * p.src_b + (oz + z) * p.src_p + (oy + y) * p.src_r + ox + x;
+                    ld_pair<S, SRCDF>(p.src, g, fx, q[2 * r], q[2 * r + 1]);
+                } else {
+                    q[2 * r] = lll[j - 2][P.at(z, y, x)];
+                    if (fx) q[2 * r + 1] = lll[j - 2][P.at(z, y, x + 1)];
+                }
             }
             block_fwd(q, fx, fy, fz);
 #pragma unroll
@@ -272,14 +311,17 @@ __device__ void inv3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
             }
             block_inv(q, fx, fy, fz);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int dx = i & 1, dy = (i >> 1) & 1, dz = i >> 2;
-                if ((dx && !fx) || (dy && !fy) || (dz && !fz)) continue;
-                const int z = 2 * bz + dz, y = 2 * by + dy, x = 2 * bx + dx;
-                if (j == 1)
-                    st_val<S, DSTDF>(p.dst, item * p.dst_b + (oz + z) * p.dst_p + (oy + y) * p.dst_r + ox + x, q[i]);
-                else
-                    lll[j - 2][P.at(z, y, x)] = q[i];
+            for (int r = 0; r < 4; ++r) {
+                const int dy = r & 1, dz = r >> 1;
+                if ((dy && !fy) || (dz && !fz)) continue;
+                const int z = 2 * bz + dz, y = 2 * by + dy, x = 2 * bx;
+                if (j == 1) {
+                    const int64_t g = item * p.dst_b + (oz + z) * p.dst_p + (oy + y) * p.dst_r + ox + x;
+                    st_pair<S, DSTDF>(p.dst, g, fx, q[2 * r], q[2 * r + 1]);
+                } else {
+                    lll[j - 2][P.at(z, y, x)] = q[2 * r];
+                    if (fx) lll[j - 2][P.at(z, y, x + 1)] = q[2 * r + 1];
+                }
             }
         }
         if (j > 1) __syncthreads();
