@@ -77,25 +77,7 @@ __device__ __forceinline__ void st_val(void* base, int64_t i, double v) {
 }
 
 // Samples i and i + 1 of a row (both when `two`, else i alone): one 8-byte
-// access of storage samples or one 16-byte access of FP64 scratch.
-template <class S, bool DF>
-__device__ __forceinline__ void ld_pair(const void* base, int64_t i, bool two, double& a, double& b) {
-    if (!two) {
-        a = ld_val<S, DF>(base, i);
-        return;
-    }
-    if constexpr (DF) {
-        const double* p = reinterpret_cast<const double*>(base) + i;
-        a = p[0];
-        b = p[1];
-    } else {
-        float f[2];
-        ld_vec<S, 2>(reinterpret_cast<const typename S::raw*>(base) + i, f);
-        a = (double)f[0];
-        b = (double)f[1];
-    }
-}
-
+// store of storage samples or one 16-byte store of FP64 scratch.
 template <class S, bool DF>
 __device__ __forceinline__ void st_pair(void* base, int64_t i, bool two, double a, double b) {
     if (!two) {
@@ -179,6 +161,9 @@ struct Blocks3 {
     __device__ __forceinline__ int at(int z, int y, int x) const { return (z << (xs + ys)) + (y << xs) + x; }
 };
 constexpr int kLll1 = 4 * 4 * 32, kLll2 = 2 * 2 * 16;   // LLL regions of levels 1 and 2 in LDS
+
+// Offset of the level-j LLL region (j = 1, 2) in the generic path's LDS.
+__device__ __forceinline__ int lll_off(int j) { return j == 1 ? 0 : kLll1; }
 constexpr int kSlots1 = kLll1 / kThreads3;              // level-1 blocks per thread
 
 // Analysis butterflies of one block with the carry rule: along an axis
@@ -235,7 +220,6 @@ __device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
     const Counts3 c = tile_counts(p, oz, oy, ox);
     const int J = p.levels;
     raw* det = reinterpret_cast<raw*>(p.det) + item * p.det_b;
-    double* lll[2] = {sm, sm + kLll1};         // LLL_1 (4 x 4 x 32), LLL_2 (2 x 2 x 16)
     for (int j = 1; j <= J; ++j) {
         const Blocks3 B(j);
         const Blocks3 P(j - 1 > 0 ? j - 1 : 1);   // layout of the level-(j-1) LLL in LDS
@@ -256,12 +240,14 @@ __device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
                 q[2 * r] = q[2 * r + 1] = 0.0;
                 if ((dy && !fy) || (dz && !fz)) continue;
                 const int z = 2 * bz + dz, y = 2 * by + dy, x = 2 * bx;
-                if (j == 1) {
+                if (j == 1) {   // per sample: pair loads measured 3x slower here
                     const int64_t g = item * p.src_b + (oz + z) * p.src_p + (oy + y) * p.src_r + ox + x;
-                    ld_pair<S, SRCDF>(p.src, g, fx, q[2 * r], q[2 * r + 1]);
+                    q[2 * r] = ld_val<S, SRCDF>(p.src, g);
+                    if (fx) q[2 * r + 1] = ld_val<S, SRCDF>(p.src, g + 1);
                 } else {
-                    q[2 * r] = lll[j - 2][P.at(z, y, x)];
-                    if (fx) q[2 * r + 1] = lll[j - 2][P.at(z, y, x + 1)];
+                    const int o = lll_off(j - 1) + P.at(z, y, x);
+                    q[2 * r] = sm[o];
+                    if (fx) q[2 * r + 1] = sm[o + 1];
                 }
             }
             block_fwd(q, fx, fy, fz);
@@ -273,7 +259,7 @@ __device__ void fwd3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
                 st_val<S, LLDF>(p.ll, item * p.ll_b + ((oz >> j) + bz) * p.ll_p + ((oy >> j) + by) * p.ll_r +
                                           (ox >> j) + bx, q[0]);
             else
-                lll[j - 1][B.at(bz, by, bx)] = q[0];
+                sm[lll_off(j) + B.at(bz, by, bx)] = q[0];
         }
         if (j < J) __syncthreads();
     }
@@ -285,7 +271,6 @@ __device__ void inv3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
     const Counts3 c = tile_counts(p, oz, oy, ox);
     const int J = p.levels;
     const raw* det = reinterpret_cast<const raw*>(p.det) + item * p.det_b;
-    double* lll[2] = {sm, sm + kLll1};
     for (int j = J; j >= 1; --j) {
         const Blocks3 B(j);
         const Blocks3 P(j - 1 > 0 ? j - 1 : 1);
@@ -302,7 +287,7 @@ __device__ void inv3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
             double q[8];
             q[0] = j == J ? ld_val<S, LLDF>(p.ll, item * p.ll_b + ((oz >> j) + bz) * p.ll_p +
                                                       ((oy >> j) + by) * p.ll_r + (ox >> j) + bx)
-                          : lll[j - 1][B.at(bz, by, bx)];
+                          : sm[lll_off(j) + B.at(bz, by, bx)];
 #pragma unroll
             for (int code = 1; code < 8; ++code) {
                 q[code] = 0.0;
@@ -319,8 +304,9 @@ __device__ void inv3d_lds(const Pass3D& p, int64_t item, int64_t oz, int64_t oy,
                     const int64_t g = item * p.dst_b + (oz + z) * p.dst_p + (oy + y) * p.dst_r + ox + x;
                     st_pair<S, DSTDF>(p.dst, g, fx, q[2 * r], q[2 * r + 1]);
                 } else {
-                    lll[j - 2][P.at(z, y, x)] = q[2 * r];
-                    if (fx) lll[j - 2][P.at(z, y, x + 1)] = q[2 * r + 1];
+                    const int o = lll_off(j - 1) + P.at(z, y, x);
+                    sm[o] = q[2 * r];
+                    if (fx) sm[o + 1] = q[2 * r + 1];
                 }
             }
         }
