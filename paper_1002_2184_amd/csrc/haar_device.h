@@ -182,18 +182,25 @@ typedef unsigned int v4u __attribute__((ext_vector_type(4), aligned(2)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2), aligned(2)));
 typedef unsigned int u32e __attribute__((aligned(2)));
 
-template <class T>
-__device__ __forceinline__ T ld_any(const T* p) {
-#if HAAR_NT_LOADS
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
+// Storage traits that address HBM (kStream) access it through global
+// address-space pointers.  A pointer read from a work list (the plans) is
+// otherwise generic, and generic (flat) instructions count against both the
+// vector-memory and the LDS wait counters.  The LDS trait (StLds) keeps
+// generic pointers.
+#define HAAR_GLOBAL __attribute__((address_space(1)))
 
-template <class T>
-__device__ __forceinline__ void st_any(T v, T* p) {
-    __builtin_nontemporal_store(v, p);
+template <class S, class T>
+__device__ __forceinline__ T ld_s(const T* p) {
+    if constexpr (S::kStream) {
+        const HAAR_GLOBAL T* g = (const HAAR_GLOBAL T*)p;
+#if HAAR_NT_LOADS
+        return __builtin_nontemporal_load(g);
+#else
+        return *g;
+#endif
+    } else {
+        return *p;
+    }
 }
 
 // Load N consecutive elements (N * kBytes in {2, 4, 8, 16}; the pointer
@@ -204,26 +211,26 @@ __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
     static_assert(B == 2 || B == 4 || B == 8 || B == 16, "vector width");
     if constexpr (S::kBytes == 4) {
         if constexpr (N == 4) {
-            const v4f v = ld_any(reinterpret_cast<const v4f*>(p));
+            const v4f v = ld_s<S>(reinterpret_cast<const v4f*>(p));
             out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
         } else if constexpr (N == 2) {
-            const v2f v = ld_any(reinterpret_cast<const v2f*>(p));
+            const v2f v = ld_s<S>(reinterpret_cast<const v2f*>(p));
             out[0] = v.x; out[1] = v.y;
         } else {
-            out[0] = ld_any(reinterpret_cast<const float*>(p));
+            out[0] = ld_s<S>(reinterpret_cast<const float*>(p));
         }
     } else {
         uint32_t w[B >= 4 ? B / 4 : 1];
         if constexpr (B == 16) {
-            const v4u v = ld_any(reinterpret_cast<const v4u*>(p));
+            const v4u v = ld_s<S>(reinterpret_cast<const v4u*>(p));
             w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
         } else if constexpr (B == 8) {
-            const v2u v = ld_any(reinterpret_cast<const v2u*>(p));
+            const v2u v = ld_s<S>(reinterpret_cast<const v2u*>(p));
             w[0] = v.x; w[1] = v.y;
         } else if constexpr (B == 4) {
-            w[0] = ld_any(reinterpret_cast<const u32e*>(p));
+            w[0] = ld_s<S>(reinterpret_cast<const u32e*>(p));
         } else {
-            out[0] = S::ld(ld_any(p));
+            out[0] = S::ld(ld_s<S>(p));
             return;
         }
 #pragma unroll
@@ -237,7 +244,7 @@ __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
 template <class S, class T>
 __device__ __forceinline__ void st_s(T v, T* p) {
     if constexpr (S::kStream)
-        st_any(v, p);
+        __builtin_nontemporal_store(v, (HAAR_GLOBAL T*)p);
     else
         *p = v;
 }
@@ -284,10 +291,15 @@ __device__ __forceinline__ void st1(typename S::raw* p, float v) { st_s<S>(S::st
 // of the deepest 2D levels: these cover only part of a cache line each, and
 // partial lines cost less through the caches than streamed.
 template <class S>
-__device__ __forceinline__ void st1_cached(typename S::raw* p, float v) { *p = S::st(v); }
+__device__ __forceinline__ void st1_cached(typename S::raw* p, float v) {
+    if constexpr (S::kStream)
+        *(HAAR_GLOBAL typename S::raw*)p = S::st(v);
+    else
+        *p = S::st(v);
+}
 
 template <class S>
-__device__ __forceinline__ float ld1(const typename S::raw* p) { return S::ld(ld_any(p)); }
+__device__ __forceinline__ float ld1(const typename S::raw* p) { return S::ld(ld_s<S>(p)); }
 
 // ceil(n / 2^j)
 __device__ __forceinline__ int64_t ceil_shift(int64_t n, int j) {
