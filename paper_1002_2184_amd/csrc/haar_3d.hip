@@ -16,8 +16,9 @@
 // Interior tiles run a register path: level 1 inside each thread
 // (2 x 2 x 2 blocks), level 2 across lanes with shuffles, level 3 on one
 // wavefront through LDS.  Edge tiles (and odd counts) run a generic path
-// that keeps the tile in LDS.  Deeper transforms chain passes through
-// scratch.
+// that takes whole 2 x 2 x 2 blocks per thread, level by level, with the
+// carry rule on each axis and only the LLL regions in LDS.  Deeper
+// transforms chain passes through scratch.
 //
 // Arithmetic: samples are widened to FP64, which gfx950 executes at the
 // rate of unpacked FP32.  One FP64 add replaces the six-operation pair sum
