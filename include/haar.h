@@ -307,7 +307,8 @@ int haar_plan_destroy(haar_plan* plan);
 /* ------------------------------------------------------------------------
  * Tuning.  haar_tune_2d times the candidate tile shapes for one problem on
  * `stream` (hipEvents; it synchronises that stream) using caller-owned
- * device scratch of at least 2 * batch * height * width * element bytes,
+ * device scratch of at least 2 * batch * height * width * element bytes
+ * + 32 (two 16-byte-aligned tensors),
  * records the fastest in the process-wide table and returns its index in
  * *choice.  The table is consulted by later plain calls and plans with the
  * same (dtype, direction, levels, size class).  haar_tune_save/load write
@@ -316,7 +317,8 @@ int haar_plan_destroy(haar_plan* plan);
 int haar_tune_2d(int32_t dtype, int32_t inverse, int64_t height, int64_t width,
                  int32_t levels, int64_t batch, void* scratch, size_t scratch_bytes,
                  void* stream, int32_t* choice);
-/* Same for the 1D chunk shapes (scratch: 2 * batch * length * element bytes). */
+/* Same for the 1D chunk shapes (scratch: 2 * batch * length * element bytes
+ * + 32). */
 int haar_tune_1d(int32_t dtype, int32_t inverse, int64_t length, int32_t levels, int64_t batch,
                  void* scratch, size_t scratch_bytes, void* stream, int32_t* choice);
 int haar_tune_save(const char* path);
