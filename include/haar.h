@@ -236,14 +236,17 @@ int haar_max_levels_3d(int64_t depth, int64_t height, int64_t width);
  *
  * A plan lists the work units of all items (2D: tiles, 1D: chunks of 4096
  * samples), largest items first, and haar_plan_execute() enqueues ONE
- * kernel that drains the list, under one of three schedules: a persistent
- * grid (the resident work-groups of the device) walking the list with a
- * stride, a persistent grid claiming units from an atomic counter, or one
- * work-group per unit.  Defaults, as measured: 2D analysis plans claim
- * their tiles (edge tiles differ in cost); 2D synthesis plans and all 1D
- * plans run one unit per work-group.  See haar_plan_set_config.  A 1D analysis plan with items deeper than 12
- * levels enqueues a second, small kernel that finishes those items, one
- * work-group per item.  The plan itself holds host memory only; the
+ * kernel that drains the list, under one of the schedules of
+ * haar_plan_set_config: a persistent grid (the resident work-groups of the
+ * device) walking the list with a stride, a persistent grid claiming units
+ * from an atomic counter, or one work-group per unit, the last for 2D also
+ * with the units of each XCD contiguous and write-back stores.  Defaults, as
+ * measured: 2D analysis plans run one tile per work-group, XCD-contiguous,
+ * with write-back stores (rows of most images start inside a cache line,
+ * and neighbouring tiles then share lines); 2D synthesis plans and all 1D
+ * plans run one unit per work-group.  A 1D analysis plan with items deeper
+ * than 12 levels enqueues a second, small kernel that finishes those items,
+ * one work-group per item.  The plan itself holds host memory only; the
  * device-side tables and counters live in a caller-owned workspace of
  * haar_plan_workspace_size() bytes (256-byte aligned).
  *
@@ -292,9 +295,11 @@ int haar_plan_info(const haar_plan* plan, int64_t* tiles, int32_t* grid);
 /* Select a plan configuration; the plan must be uploaded again.  The
  * schedule is 0: a persistent grid of G work-groups, work-group b runs units
  * b, b + G, b + 2G, ... of the list; 1: a persistent grid whose work-groups
- * claim units from an atomic counter; 2: one work-group per unit.
+ * claim units from an atomic counter; 2: one work-group per unit; 3 (2D
+ * only): one work-group per unit, the units of each XCD contiguous in the
+ * list, outputs written with write-back instead of streaming stores.
  * 2D: config = tile shape + 2 * schedule, tile shape 0: 32 rows x 16
- * vectors, 1: 32 rows x 32 vectors (configs 0..5).  1D: config = schedule
+ * vectors, 1: 32 rows x 32 vectors (configs 0..7).  1D: config = schedule
  * (0..2). */
 int haar_plan_set_config(haar_plan* plan, int32_t config);
 /* Autotune a plan: time executes of every configuration on `stream`

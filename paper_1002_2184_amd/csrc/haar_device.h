@@ -122,7 +122,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 }
 
 struct StF32 {
-    static constexpr bool kStream = true;   // outputs go to HBM with streaming stores
+    static constexpr bool kStream = true;   // HBM, addressed through global pointers
+    static constexpr bool kNT = true;       // outputs written with streaming stores
     using raw = float;
     static constexpr int kBytes = 4;
     __device__ __forceinline__ static float ld(raw v) { return v; }
@@ -130,7 +131,8 @@ struct StF32 {
 };
 
 struct StBF16 {
-    static constexpr bool kStream = true;   // outputs go to HBM with streaming stores
+    static constexpr bool kStream = true;   // HBM, addressed through global pointers
+    static constexpr bool kNT = true;       // outputs written with streaming stores
     using raw = uint16_t;
     static constexpr int kBytes = 2;
     __device__ __forceinline__ static float ld(raw v) { return __uint_as_float((uint32_t)v << 16); }
@@ -142,6 +144,7 @@ struct StBF16 {
 // LDS, addressed through generic pointers): ordinary stores.
 struct StLds {
     static constexpr bool kStream = false;
+    static constexpr bool kNT = false;
     using raw = float;
     static constexpr int kBytes = 4;
     __device__ __forceinline__ static float ld(raw v) { return v; }
@@ -149,7 +152,8 @@ struct StLds {
 };
 
 struct StF16 {
-    static constexpr bool kStream = true;   // outputs go to HBM with streaming stores
+    static constexpr bool kStream = true;   // HBM, addressed through global pointers
+    static constexpr bool kNT = true;       // outputs written with streaming stores
     using raw = uint16_t;
     static constexpr int kBytes = 2;
     __device__ __forceinline__ static float ld(raw v) {
@@ -243,11 +247,23 @@ __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
 
 template <class S, class T>
 __device__ __forceinline__ void st_s(T v, T* p) {
-    if constexpr (S::kStream)
+    if constexpr (S::kStream && S::kNT)
         __builtin_nontemporal_store(v, (HAAR_GLOBAL T*)p);
+    else if constexpr (S::kStream)
+        *(HAAR_GLOBAL T*)p = v;
     else
         *p = v;
 }
+
+// The same storage format written with ordinary (write-back) stores.  When
+// rows do not start on cache-line boundaries, the first and last line of
+// every row piece of a tile is shared with the neighbouring tile; written
+// back through the L2 that both tiles use, the two halves merge there, where
+// two streaming partial-line writes would each go to HBM.
+template <class S>
+struct WriteBack : S {
+    static constexpr bool kNT = false;
+};
 
 template <class S, int N>
 __device__ __forceinline__ void st_vec(typename S::raw* p, const float* v) {

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <mutex>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 #include "haar.h"
@@ -85,8 +86,11 @@ __device__ __forceinline__ void retire(unsigned* ctr) {
 // atomic counter (balances units of very different cost); otherwise unit
 // b, b + G, b + 2G, ... (no atomics; the units of a plan are nearly uniform
 // and sorted largest item first).  The unit index is made wavefront-uniform
-// so that the descriptors come through the scalar cache.
-template <bool DYN, class F>
+// so that the descriptors come through the scalar cache.  REMAP (one unit per
+// work-group): work-groups are dealt round-robin to the 8 XCDs, so block b
+// takes unit xcd_tile(b), which gives every XCD one contiguous range of the
+// list; neighbouring tiles of an image then run on one XCD and share its L2.
+template <bool DYN, bool REMAP, class F>
 __device__ __forceinline__ void walk_units(unsigned n, unsigned* ctr, unsigned* s_slot, F&& body) {
     if constexpr (DYN) {
         unsigned unit;
@@ -96,23 +100,28 @@ __device__ __forceinline__ void walk_units(unsigned n, unsigned* ctr, unsigned* 
         }
         retire(ctr);
     } else {
+        const bool remap = REMAP && gridDim.x == n;
         for (unsigned unit = blockIdx.x; unit < n; unit += gridDim.x) {
-            body(unit);
+            body(remap ? (unsigned)xcd_tile(unit, n) : unit);
             __syncthreads();
         }
     }
 }
 
-template <class S, int GY, int GX, bool INV, bool DYN>
+// WB: XCD-contiguous units and write-back stores (WriteBack<S>), so that the
+// partial cache lines that neighbouring tiles of a misaligned image share are
+// merged in L2 instead of being streamed to HBM twice.
+template <class S, int GY, int GX, bool INV, bool DYN, bool WB>
 __global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __restrict__ items,
                                                         const PlanTile2D* __restrict__ tiles,
                                                         unsigned ntiles, unsigned* ctr) {
     constexpr int RX = 16 / S::kBytes;
+    using SO = std::conditional_t<WB, WriteBack<S>, S>;   // storage of the outputs
     using G = Geo2D<S, 4, RX, GY, GX>;
     constexpr int SM_FWD = G::SMEM, SM_INV = G::AN + G::BN + G::QPT * G::NT;
     __shared__ float sm[SM_FWD > SM_INV ? SM_FWD : SM_INV];
     __shared__ unsigned s_slot;
-    walk_units<DYN>(ntiles, ctr, &s_slot, [&](unsigned unit) {
+    walk_units<DYN, WB>(ntiles, ctr, &s_slot, [&](unsigned unit) {
         const PlanTile2D d = tiles[unit];
         const PlanItem2D it = items[d.item];
         Pass2D p{};
@@ -136,22 +145,22 @@ __global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __rest
             if (d.full) {
                 FwdIn<4, RX> in;
                 fwd2d_load<S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in);
-                fwd2d_body<S, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in, sm);
+                fwd2d_body<S, SO, SO, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in, sm);
             } else {
                 FwdIn<4, RX> in;
                 fwd2d_load<S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in);
-                fwd2d_body<S, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in, sm);
+                fwd2d_body<S, SO, SO, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in, sm);
             }
         } else {
-            using In = InvInT<S, S, S, 4, RX, GY, GX>;
+            using In = InvInT<SO, S, S, 4, RX, GY, GX>;
             if (d.full) {
                 In in;
-                inv2d_load<S, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in);
-                inv2d_body<S, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in, sm);
+                inv2d_load<SO, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in);
+                inv2d_body<SO, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in, sm);
             } else {
                 In in;
-                inv2d_load<S, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in);
-                inv2d_body<S, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in, sm);
+                inv2d_load<SO, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in);
+                inv2d_body<SO, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in, sm);
             }
         }
     });
@@ -169,7 +178,7 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
     __shared__ float smf[NW * 8];
     __shared__ float stage[kPlanC1];
     __shared__ unsigned s_slot;
-    walk_units<DYN>(nunits, ctr, &s_slot, [&](unsigned unit) {
+    walk_units<DYN, false>(nunits, ctr, &s_slot, [&](unsigned unit) {
         const PlanChunk1D d = chunks[unit];
         const PlanItem1D it = items[d.item];
         Pass1D p{};
@@ -240,7 +249,8 @@ struct haar_plan {
     int dtype = 0;
     int inverse = 0;
     int cfg = 1;                       // 2D tile configuration (0: 32 rows x 16 vectors, 1: x 32)
-    int sched = 0;                     // 0: strided work-list walk, 1: atomic claiming, 2: one unit per work-group
+    int sched = 0;                     // 0: strided work-list walk, 1: atomic claiming, 2: one unit per
+                                       // work-group, 3 (2D): 2 with XCD-contiguous units, write-back stores
     std::vector<PlanItem2D> items2;
     std::vector<PlanTile2D> tiles2[2];  // per tile configuration
     std::vector<PlanItem1D> items1;
@@ -256,7 +266,8 @@ struct haar_plan {
 namespace {
 
 constexpr int kPlanCfgs2D = 2;          // tile configurations with plan kernels: 0 and 1
-constexpr int kPlanScheds = 3;          // 0 strided walk, 1 atomic claiming, 2 one unit per work-group
+constexpr int kPlanScheds1D = 3;        // 0 strided walk, 1 atomic claiming, 2 one unit per work-group
+constexpr int kPlanScheds2D = 4;        // the same, and 3: 2 with XCD-contiguous units and write-back stores
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -295,13 +306,21 @@ hipError_t launch_plan2d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
         hipLaunchKernelGGL(kernel, dim3(g), dim3(threads), 0, s, items, tiles, n, ctr);
         return hipGetLastError();
     };
-    const bool inv = pl->inverse != 0, dyn = pl->sched == 1;
+    const bool inv = pl->inverse != 0, dyn = pl->sched == 1, wb = pl->sched == 3;
     if (pl->cfg == 0) {
-        if (dyn) return inv ? go(plan2d_kernel<S, 8, 32, true, true>, 256) : go(plan2d_kernel<S, 8, 32, false, true>, 256);
-        return inv ? go(plan2d_kernel<S, 8, 32, true, false>, 256) : go(plan2d_kernel<S, 8, 32, false, false>, 256);
+        if (dyn) return inv ? go(plan2d_kernel<S, 8, 32, true, true, false>, 256)
+                            : go(plan2d_kernel<S, 8, 32, false, true, false>, 256);
+        if (wb) return inv ? go(plan2d_kernel<S, 8, 32, true, false, true>, 256)
+                           : go(plan2d_kernel<S, 8, 32, false, false, true>, 256);
+        return inv ? go(plan2d_kernel<S, 8, 32, true, false, false>, 256)
+                   : go(plan2d_kernel<S, 8, 32, false, false, false>, 256);
     }
-    if (dyn) return inv ? go(plan2d_kernel<S, 8, 64, true, true>, 512) : go(plan2d_kernel<S, 8, 64, false, true>, 512);
-    return inv ? go(plan2d_kernel<S, 8, 64, true, false>, 512) : go(plan2d_kernel<S, 8, 64, false, false>, 512);
+    if (dyn) return inv ? go(plan2d_kernel<S, 8, 64, true, true, false>, 512)
+                        : go(plan2d_kernel<S, 8, 64, false, true, false>, 512);
+    if (wb) return inv ? go(plan2d_kernel<S, 8, 64, true, false, true>, 512)
+                       : go(plan2d_kernel<S, 8, 64, false, false, true>, 512);
+    return inv ? go(plan2d_kernel<S, 8, 64, true, false, false>, 512)
+               : go(plan2d_kernel<S, 8, 64, false, false, false>, 512);
 }
 
 template <class S>
@@ -343,12 +362,12 @@ hipError_t launch_plan(const haar_plan* pl, void* ws, hipStream_t s, bool query_
     }
 }
 
-// Plan configurations: 2D, tile shape + 2 * schedule (0..3); 1D, the schedule (0, 1).
-int plan_configs(const haar_plan* pl) { return pl->dim == 2 ? kPlanScheds * kPlanCfgs2D : kPlanScheds; }
+// Plan configurations: 2D, tile shape + 2 * schedule (0..7); 1D, the schedule (0..2).
+int plan_configs(const haar_plan* pl) { return pl->dim == 2 ? kPlanScheds2D * kPlanCfgs2D : kPlanScheds1D; }
 
 int unit_grid(const haar_plan* pl, unsigned n, int resident) {
     const int64_t units = std::max<int64_t>(1, n);
-    if (pl->sched == 2) return (int)std::min<int64_t>(units, kPlanGridCap);
+    if (pl->sched >= 2) return (int)std::min<int64_t>(units, kPlanGridCap);
     return (int)std::min<int64_t>(resident, units);
 }
 int plan_config_index(const haar_plan* pl) {
@@ -423,16 +442,19 @@ int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype,
         delete pl;
         return set_error(HAAR_ERR_SHAPE, "plan has too many tiles");
     }
-    // measured defaults (512 uneven images, 4 levels): the analysis claims
-    // its tiles (edge tiles differ in cost), 32 x 32-vector tiles (BF16 0.89
-    // ms, FP32 1.36 ms); the synthesis runs one tile per work-group, 32 x 16
-    // vectors for 16-bit data (0.73 ms against 0.87 ms claimed) and 32 x 32
-    // for FP32 (1.08 ms against 1.22 ms)
-    const int fb = inverse && dtype != 0 ? 0 : 1;
+    // measured defaults (512 uneven images, 4 levels; almost all rows of
+    // such images start inside a cache line): the analysis runs one tile per
+    // work-group with XCD-contiguous tiles and write-back stores (BF16 0.71
+    // ms against 0.87 ms claiming tiles with streaming stores, FP32 1.06
+    // against 1.33 ms); the synthesis runs one tile per work-group with
+    // streaming stores (BF16 0.72 ms against 0.78 ms with the XCD-contiguous
+    // write-back schedule).  Tiles of 32 x 16 vectors for 16-bit data, 32 x
+    // 32 for FP32.
+    const int fb = dtype != 0 ? 0 : 1;
     const int c = choose_config_2d(dtype, inverse != 0, items[order[0]].height, items[order[0]].width,
                                    items[order[0]].levels, fb);
     pl->cfg = tile_config_2d(eb, c).gx == 32 ? 0 : 1;
-    pl->sched = inverse ? 2 : 1;
+    pl->sched = inverse ? 2 : 3;
     layout(pl, sizeof(PlanItem2D), pl->items2.size(), sizeof(PlanTile2D),
            (int64_t)std::max(pl->tiles2[0].size(), pl->tiles2[1].size()), 2);
     pl->nunits = (int64_t)pl->tiles2[pl->cfg].size();

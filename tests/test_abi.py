@@ -201,9 +201,9 @@ def test_plan_validation_and_sizes(abi, monkeypatch):
     # 32x256 f32 tiles: 64x96 -> 2x1, 33x300 -> 2x2
     assert tiles.value == 6
     assert abi.haar_plan_execute(plan, X, 0) == 8          # not uploaded
-    assert abi.haar_plan_set_config(plan, 6) == 9           # configs 0..5 (shape + 2 * schedule)
+    assert abi.haar_plan_set_config(plan, 8) == 9           # configs 0..7 (shape + 2 * schedule)
     assert abi.haar_plan_set_config(plan, -1) == 9
-    assert abi.haar_plan_set_config(plan, 5) == 0
+    assert abi.haar_plan_set_config(plan, 7) == 0
     monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")
     assert abi.haar_plan_upload(plan, X, 0) == 7             # stopped before any HIP call
     assert abi.haar_plan_upload(plan, X + 8, 0) == 6         # misaligned workspace
@@ -224,6 +224,8 @@ def test_plan_1d_validation(abi):
     tiles = ctypes.c_int64()
     assert abi.haar_plan_info(plan, ctypes.byref(tiles), None) == 0
     assert tiles.value == 1 + 256 + 1
+    assert abi.haar_plan_set_config(plan, 3) == 9           # 1D: schedules 0..2 only
+    assert abi.haar_plan_set_config(plan, 2) == 0
     assert abi.haar_plan_destroy(plan) == 0
     deep = (abi.Item1D * 1)(abi.Item1D(X, Y + (1 << 40), 1 << 23, 23))
     assert abi.haar_plan_create_1d(deep, 1, 0, 0, ctypes.byref(plan)) == 9

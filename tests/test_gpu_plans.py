@@ -72,20 +72,61 @@ def test_plan2d_configs_and_tune(P):
     lv = _lv(SHAPES_2D, 4)
     plan = P.Plan2D(xd, yd, lv)
     refs = [oracle.fwd_2d(x.astype(np.float64), L) for x, L in zip(xs, lv)]
-    for cfg in range(6):              # tile shape + 2 * schedule (strided, atomic claiming, one tile per WG)
+    # tile shape + 2 * schedule (strided, atomic claiming, one tile per WG,
+    # one tile per WG XCD-contiguous with write-back stores)
+    for cfg in range(8):
         plan.set_config(cfg)
         plan.execute()
         torch.cuda.synchronize()
         for y, r, x in zip(yd, refs, xs):
             check_signal(to_host(y, G.F32).astype(np.float64), r, rms(x), G.F32, f"config {cfg}")
     choice = plan.tune()
-    assert choice in range(6)
+    assert choice in range(8)
     plan.execute()
     torch.cuda.synchronize()
     for y, r, x in zip(yd, refs, xs):
         check_signal(to_host(y, G.F32).astype(np.float64), r, rms(x), G.F32, "tuned")
     tiles, grid = plan.info()
     assert tiles > 0 and 1 <= grid <= tiles
+
+
+@pytest.mark.parametrize("dt", [G.F32, G.BF16])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_plan2d_every_config_both_directions(P, dt, inverse):
+    """All 8 configurations (2 tile shapes x 4 schedules) of an analysis and of
+    a synthesis plan, two executes each, on images whose rows mostly start
+    inside a cache line (odd and even widths, widths not a multiple of 64)."""
+    import torch
+    shapes = SHAPES_2D + [(96, 1030), (18, 2050), (300, 44)]
+    L = 4
+    lv = _lv(shapes, L)
+    xs = _imgs(dt, shapes, seed=41 + dt + 2 * inverse)
+    if inverse:
+        ins = [G.to_storage(oracle.fwd_2d(G.widen(x, dt), l), dt) for x, l in zip(xs, lv)]
+        refs = [oracle.inv_2d(G.widen(c, dt), l) for c, l in zip(ins, lv)]
+    else:
+        ins = xs
+        refs = [oracle.fwd_2d(G.widen(x, dt), l) for x, l in zip(xs, lv)]
+    xd = [to_device(x, dt) for x in ins]
+    yd = [torch.empty_like(x) for x in xd]
+    plan = P.Plan2D(xd, yd, lv, inverse=inverse)
+    for cfg in range(8):
+        plan.set_config(cfg)
+        for rep in range(2):
+            for y in yd:
+                y.fill_(float("nan"))
+            plan.execute()
+            torch.cuda.synchronize()
+            for x, y, r, s, l in zip(ins, yd, refs, shapes, lv):
+                yw = G.widen(to_host(y, dt), dt)
+                scale = rms(G.widen(x, dt))
+                what = f"{'inv' if inverse else 'fwd'} config {cfg} rep {rep} {s} L={l}"
+                if dt == G.F32:
+                    check_signal(yw, r, scale, dt, what)
+                elif inverse:
+                    check_lowp_signal(yw, r, scale, dt, what)
+                else:
+                    check_lowp_coeffs(yw, r, scale, dt, band_views(s, l), what)
 
 
 LENGTHS_1D = [1 << 20, 65536, 100003, 8192, 5000, 4096, 4095, 1024, 777, 1 << 17, 3 * 4096]
