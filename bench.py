@@ -141,14 +141,18 @@ def write_traffic(fetch_csv: str, write_csv: str, command: str):
     print(json.dumps(doc))
 
 
-def write_kernel_stats(stats_csv: str, command: str, out_md: str):
+def write_kernel_stats(stats_csv: str, command: str, out_md: str, max_rows: int = 30):
     """Summarise a rocprofv3 --kernel-trace --stats CSV (one row per kernel
     name) into a short Markdown table under profiles/."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = len(rows)
+    rows = rows[:max_rows]
     with open(out_md, "w") as f:
         f.write(f"# Kernel durations (rocprofv3 --kernel-trace --stats)\n\nCommand: `{command}`\n\n")
+        if total > len(rows):
+            f.write(f"The {len(rows)} kernels with the most GPU time, of {total}.\n\n")
         f.write("| kernel | calls | average us | min us | max us | share of GPU time |\n|---|---|---|---|---|---|\n")
         for r in rows:
             name = r["Name"]

@@ -42,13 +42,12 @@ __device__ __forceinline__ void tile_coords(const Pass2D& p, int64_t tile, int64
     }
 }
 
-// Interior launches are persistent and software pipelined: a work-group
-// walks tiles b, b + G, b + 2G, ... and issues the HBM reads of its next tile
-// before it computes and writes the current one, so that reads stay in
-// flight while the tile's LDS levels and stores run.  Edge launches process
-// one tile per work-group on the scalar path.
+// Persistent launches (the tuner's persistent configurations, and grids
+// beyond kMaxGrid tiles): a work-group walks tiles b, b + G, b + 2G, ...;
+// with PIPE it issues the HBM reads of its next tile before it computes and
+// writes the current one.  Interior and edge tiles are separate launches.
 template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE, bool PIPE, int MAP>
-__global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D p, int64_t ntiles) {
+__global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_persistent_kernel(Pass2D p, int64_t ntiles) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
     __shared__ float sm[G::SMEM];
     const bool remap = p.remap && (int64_t)gridDim.x == ntiles;
@@ -82,10 +81,8 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D
 }
 
 template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool EDGE, bool PIPE>
-__global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D p, int64_t ntiles) {
-    using G = Geo2D<SX, RY, RX, GY, GX>;
+__global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_persistent_kernel(Pass2D p, int64_t ntiles) {
     using In = InvInT<SX, SD, SL, RY, RX, GY, GX>;
-    __shared__ float sm[G::AN + G::BN + G::QPT * G::NT];
     const bool remap = p.remap && (int64_t)gridDim.x == ntiles;
     int64_t b = blockIdx.x;
     if (b >= ntiles) return;
@@ -101,9 +98,8 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D
             tile_coords<EDGE>(p, nb, nitem, nty, ntx);
             inv2d_load<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, nitem, nty, ntx, nxt);
         }
-        inv2d_body<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, cur, sm);
+        inv2d_body<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, item, ty, tx, cur);
         if (nb >= ntiles) break;
-        __syncthreads();
         if (!PIPE) {
             tile_coords<EDGE>(p, nb, nitem, nty, ntx);
             inv2d_load<SX, SD, SL, RY, RX, GY, GX, !EDGE>(p, nitem, nty, ntx, nxt);
@@ -113,6 +109,56 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D
         item = nitem;
         ty = nty;
         tx = ntx;
+    }
+}
+
+// One tile per work-group, every tile of the transform in one launch: the
+// first nedge work-groups take the partial tiles (scalar path), the rest the
+// full tiles (vector path).  A separate edge launch would wait for the
+// interior launch to drain and then run its few hundred work-groups alone,
+// each bound by its own memory latency (measured: 4096 x 4128 FP32 analysis
+// 40 us in two launches, 33 us in one).  Straight-line code without a tile
+// loop also needs fewer registers than the persistent kernels.
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, int MAP>
+__global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D p, int64_t nedge,
+                                                                         int64_t ninterior) {
+    using G = Geo2D<SX, RY, RX, GY, GX>;
+    __shared__ float sm[G::SMEM];
+    const int64_t b = blockIdx.x;
+    int64_t item, ty, tx;
+    FwdIn<RY, RX> in;
+    if (b < nedge) {
+        tile_coords<true>(p, b, item, ty, tx);
+        fwd2d_load<SX, RY, RX, GY, GX, false, MAP>(p, item, ty, tx, in);
+        fwd2d_body<SX, SD, SL, RY, RX, GY, GX, false, MAP>(p, item, ty, tx, in, sm);
+    } else {
+        const int64_t t = b - nedge;
+        // (XCD-contiguous order only when the edge blocks leave the round-robin
+        // dealing of blocks to XCDs aligned: block b goes to XCD b mod 8)
+        tile_coords<false>(p, (p.remap && (nedge & 7) == 0) ? xcd_tile(t, ninterior) : t, item, ty, tx);
+        fwd2d_load<SX, RY, RX, GY, GX, true, MAP>(p, item, ty, tx, in);
+        fwd2d_body<SX, SD, SL, RY, RX, GY, GX, true, MAP>(p, item, ty, tx, in, sm);
+    }
+}
+
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX>
+__global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D p, int64_t nedge,
+                                                                         int64_t ninterior) {
+    using In = InvInT<SX, SD, SL, RY, RX, GY, GX>;
+    const int64_t b = blockIdx.x;
+    int64_t item, ty, tx;
+    In in;
+    if (b < nedge) {
+        tile_coords<true>(p, b, item, ty, tx);
+        inv2d_load<SX, SD, SL, RY, RX, GY, GX, false>(p, item, ty, tx, in);
+        inv2d_body<SX, SD, SL, RY, RX, GY, GX, false>(p, item, ty, tx, in);
+    } else {
+        const int64_t t = b - nedge;
+        // (XCD-contiguous order only when the edge blocks leave the round-robin
+        // dealing of blocks to XCDs aligned: block b goes to XCD b mod 8)
+        tile_coords<false>(p, (p.remap && (nedge & 7) == 0) ? xcd_tile(t, ninterior) : t, item, ty, tx);
+        inv2d_load<SX, SD, SL, RY, RX, GY, GX, true>(p, item, ty, tx, in);
+        inv2d_body<SX, SD, SL, RY, RX, GY, GX, true>(p, item, ty, tx, in);
     }
 }
 
@@ -162,26 +208,37 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     constexpr int64_t kMaxGrid = 1 << 20;
     const int64_t interior = p.vec_ok ? p.full_x * p.full_y * p.batch : 0;
     const int64_t edge = p.total_tiles - interior;
+    if (p.persist == 0 && p.total_tiles <= kMaxGrid) {
+        if (p.total_tiles <= 0) return hipSuccess;
+        const unsigned grid = (unsigned)p.total_tiles;
+        if (inverse)
+            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX>), dim3(grid), dim3(GY * GX), 0, s, p,
+                               edge, interior);
+        else
+            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, MAP>), dim3(grid), dim3(GY * GX), 0,
+                               s, p, edge, interior);
+        return hipGetLastError();
+    }
     if (interior > 0) {
         const int64_t cap = p.persist > 0 ? p.persist : kMaxGrid;
         const unsigned grid = (unsigned)(interior < cap ? interior : cap);
         if (inverse)
-            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE>), dim3(grid),
+            hipLaunchKernelGGL((inv2d_persistent_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE>), dim3(grid),
                                dim3(GY * GX), 0, s, p, interior);
         else
-            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE, MAP>), dim3(grid),
-                               dim3(GY * GX), 0, s, p, interior);
+            hipLaunchKernelGGL((fwd2d_persistent_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE, MAP>),
+                               dim3(grid), dim3(GY * GX), 0, s, p, interior);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (edge > 0) {
         const unsigned grid = (unsigned)(edge < kMaxGrid ? edge : kMaxGrid);
         if (inverse)
-            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, true, false>), dim3(grid),
+            hipLaunchKernelGGL((inv2d_persistent_kernel<SX, SD, SL, 4, RX, GY, GX, true, false>), dim3(grid),
                                dim3(GY * GX), 0, s, p, edge);
         else
-            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, true, false, MAP>), dim3(grid),
-                               dim3(GY * GX), 0, s, p, edge);
+            hipLaunchKernelGGL((fwd2d_persistent_kernel<SX, SD, SL, 4, RX, GY, GX, true, false, MAP>),
+                               dim3(grid), dim3(GY * GX), 0, s, p, edge);
         return hipGetLastError();
     }
     return hipSuccess;

@@ -88,6 +88,19 @@ __device__ __forceinline__ void syn_edge(float ll, float hl, float lh, float hh,
     }
 }
 
+// The child (dy, dx) of one synthesis block, with the carry rule: the same
+// arithmetic as syn_edge for that output.
+__device__ __forceinline__ float syn_child(float ll, float hl, float lh, float hh, bool r1, bool c1,
+                                           int dy, int dx) {
+    if (r1 && c1) {
+        const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
+        return 0.5f * (dx ? base + tt : base - tt);
+    }
+    if (c1) return (dx ? ll + hl : ll - hl) * kRs2Hi;
+    if (r1) return (dy ? ll + lh : ll - lh) * kRs2Hi;
+    return ll;
+}
+
 // ---------------------------------------------------------------------------
 // Analysis tile
 // ---------------------------------------------------------------------------
@@ -102,10 +115,6 @@ struct Geo2D {
     static constexpr int AN = (TH / 4) * (TW / 4);   // LDS buffer A: LL2 region
     static constexpr int BN = (TH / 8) * (TW / 8);   // LDS buffer B: LL3 region
     static constexpr int SMEM = 2 * AN + 2 * BN;     // floats (hi + lo each)
-    // synthesis: LL_L and the detail bands of levels 3..L (L <= 5) of one tile
-    static constexpr int R3 = (TH >> 3) * (TW >> 3), R4 = (TH >> 4) * (TW >> 4), R5 = (TH >> 5) * (TW >> 5);
-    static constexpr int QMAX = 3 * (R3 + R4 + R5) + R3;      // >= the count for any L <= 5
-    static constexpr int QPT = (QMAX + NT - 1) / NT;           // prefetched values per thread
     static_assert(RY == 4 && RX * SX::kBytes == 16, "register block is 4 rows x 16 bytes");
     static_assert(TH % 32 == 0 && TW % 32 == 0, "tile must hold whole 32x32 blocks");
 };
@@ -495,31 +504,22 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
 // small levels (LL_L and the bands of levels 3..L, one flat index space:
 // level by level HL, LH, HH, then LL_L) and the level-1/2 details of its
 // register block.
-template <int QPT, int B1Y, int B1X, int B2Y, int B2X>
+template <int B1Y, int B1X, int B2Y, int B2X>
 struct InvIn {
-    float pre[QPT];      // edge tiles: share of the small levels, staged through LDS
-    float walk[10];      // interior tiles: LL_L, then (HL, LH, HH) of levels 3, 4, 5 on the
-                         // ancestor path of this thread's LL3 coefficient
+    float walk[10];      // LL_L, then (HL, LH, HH) of levels 3, 4, 5 on the ancestor path of
+                         // this thread's LL3 coefficient
     float hl1[B1Y][B1X], lh1[B1Y][B1X], hh1[B1Y][B1X];
     float hl2[B2Y][B2X], lh2[B2Y][B2X], hh2[B2Y][B2X];
 };
 
 template <class SX, class SD, class SL, int RY, int RX, int GY, int GX>
-using InvInT = InvIn<Geo2D<SX, RY, RX, GY, GX>::QPT, RY / 2, RX / 2, RY / 4, RX / 4>;
-
-// number of prefetched small-level values of a tile of L levels (L >= 3)
-template <int TH, int TW>
-__device__ __forceinline__ int small_count(int L) {
-    int off = 0;
-    for (int lev = 3; lev <= L; ++lev) off += 3 * (TH >> lev) * (TW >> lev);
-    return off + (TH >> L) * (TW >> L);
-}
+using InvInT = InvIn<RY / 2, RX / 2, RY / 4, RX / 4>;
 
 template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
 __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
                                            InvInT<SX, SD, SL, RY, RX, GY, GX>& in) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
-    constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
+    constexpr int TH = G::TH, TW = G::TW;
     constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
     const int t = threadIdx.x, rg = t / GX, cg = t % GX;
     const int64_t r0 = ty * TH, c0 = tx * TW;
@@ -533,56 +533,34 @@ __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_
     const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
     const int64_t dp = p.det_pitch, lp = p.ll_pitch;
 
-    // ---- interior tiles: the ancestor path of this thread's LL3 coefficient,
-    // LL_L then (HL, LH, HH) of levels L..3, loaded first (many lanes share
-    // these addresses, so most requests hit in cache)
-    if (FULL && L >= 3) {
+    // ---- the ancestor path of this thread's LL3 coefficient: LL_L, then
+    // (HL, LH, HH) of levels 3..L (many lanes share these addresses, so most
+    // requests hit in cache).  Edge tiles load only the coefficients that
+    // exist under the carry rule: HL(i, k) of level j needs column 2k + 1 of
+    // the level-(j-1) region, LH(i, k) row 2i + 1, HH both.
+    if (L >= 3) {
         const int64_t R3 = ((r0 >> 2) + (lr0 >> 2)) >> 1, C3 = ((c0 >> 2) + (lc0 >> 2)) >> 1;
-        in.walk[0] = ld1<SL>(llp + (R3 >> (L - 3)) * lp + (C3 >> (L - 3)));
+        const int64_t RL = R3 >> (L - 3), CL = C3 >> (L - 3);
+        const bool ll_in = FULL || (RL < ceil_shift(p.h, L) && CL < ceil_shift(p.w, L));
+        in.walk[0] = ll_in ? ld1<SL>(llp + RL * lp + CL) : 0.0f;
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj) {
             const int j = 3 + jj;
             if (j <= L) {
                 const int64_t hs = ceil_shift(p.h, j), ws = ceil_shift(p.w, j);
                 const int64_t R = R3 >> (j - 3), C = C3 >> (j - 3);
-                in.walk[1 + 3 * jj] = ld1<SD>(det + R * dp + ws + C);
-                in.walk[2 + 3 * jj] = ld1<SD>(det + (hs + R) * dp + C);
-                in.walk[3 + 3 * jj] = ld1<SD>(det + (hs + R) * dp + ws + C);
-            }
-        }
-    }
-    // ---- edge tiles: small levels first, so that they are the first to arrive
-    if (!FULL && L >= 3) {
-#pragma unroll
-        for (int u = 0; u < G::QPT; ++u) {
-            const int q = t + u * NT;
-            in.pre[u] = 0.0f;
-            int off = 0;
-            for (int lev = 3; lev <= L + 1; ++lev) {
-                const int lv = lev <= L ? lev : L;
-                const int rows = TH >> lv, cols = TW >> lv;
-                const int cnt = lev <= L ? 3 * rows * cols : rows * cols;
-                if (q >= off && q < off + cnt) {
-                    const int e = q - off;
-                    const int band = lev <= L ? e / (rows * cols) : 3;   // 3 = LL_L
-                    const int ij = e - (lev <= L ? band : 0) * rows * cols;
-                    const int i = ij / cols, k = ij - i * cols;
-                    const int oh = (int)ceil_shift(th, lv - 1), ow = (int)ceil_shift(tw, lv - 1);
-                    const int rh = (int)ceil_shift(th, lv), rw = (int)ceil_shift(tw, lv);
-                    const int64_t hs = ceil_shift(p.h, lv), ws = ceil_shift(p.w, lv);
-                    const int64_t R = (r0 >> lv) + i, C = (c0 >> lv) + k;
-                    if (band == 0) {          // HL: rows of LL_lv, odd column pairs
-                        if (i < rh && 2 * k + 1 < ow) in.pre[u] = ld1<SD>(det + R * dp + ws + C);
-                    } else if (band == 1) {   // LH
-                        if (2 * i + 1 < oh && k < rw) in.pre[u] = ld1<SD>(det + (hs + R) * dp + C);
-                    } else if (band == 2) {   // HH
-                        if (2 * i + 1 < oh && 2 * k + 1 < ow)
-                            in.pre[u] = ld1<SD>(det + (hs + R) * dp + ws + C);
-                    } else {                  // LL_L
-                        if (i < rh && k < rw) in.pre[u] = ld1<SL>(llp + R * lp + C);
-                    }
+                if (FULL) {
+                    in.walk[1 + 3 * jj] = ld1<SD>(det + R * dp + ws + C);
+                    in.walk[2 + 3 * jj] = ld1<SD>(det + (hs + R) * dp + C);
+                    in.walk[3 + 3 * jj] = ld1<SD>(det + (hs + R) * dp + ws + C);
+                } else {
+                    const bool r1 = 2 * R + 1 < ceil_shift(p.h, j - 1);
+                    const bool c1 = 2 * C + 1 < ceil_shift(p.w, j - 1);
+                    const bool ri = R < hs, ci = C < ws;
+                    in.walk[1 + 3 * jj] = (ri && c1) ? ld1<SD>(det + R * dp + ws + C) : 0.0f;
+                    in.walk[2 + 3 * jj] = (r1 && ci) ? ld1<SD>(det + (hs + R) * dp + C) : 0.0f;
+                    in.walk[3 + 3 * jj] = (r1 && c1) ? ld1<SD>(det + (hs + R) * dp + ws + C) : 0.0f;
                 }
-                off += cnt;
             }
         }
     }
@@ -636,9 +614,9 @@ __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_
 
 template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
 __device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
-                                           const InvInT<SX, SD, SL, RY, RX, GY, GX>& in, float* sm) {
+                                           const InvInT<SX, SD, SL, RY, RX, GY, GX>& in) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
-    constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
+    constexpr int TH = G::TH, TW = G::TW;
     constexpr int B1Y = G::B1Y, B1X = G::B1X, B2Y = G::B2Y, B2X = G::B2X;
 
     const int t = threadIdx.x, rg = t / GX, cg = t % GX;
@@ -661,81 +639,50 @@ __device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_
     const auto& hl2 = in.hl2;
     const auto& lh2 = in.lh2;
     const auto& hh2 = in.hh2;
-    const int nq = L >= 3 ? small_count<TH, TW>(L) : 0;
-    const auto& pre = in.pre;
-
-    // ---- levels L..3 in LDS from the prefetched values, producing the LL2
-    // region in buffer A (pitch TW/4) (edge tiles)
-    float* A = sm;
-    float* B = sm + G::AN;
-    float* D = sm + G::AN + G::BN;
-    if (!FULL && L >= 3) {
-#pragma unroll
-        for (int u = 0; u < G::QPT; ++u)
-            if (t + u * NT < nq) D[t + u * NT] = pre[u];
-        __syncthreads();
-        int off = 0;
-        int offs[6];
-        for (int lev = 3; lev <= L; ++lev) {
-            offs[lev] = off;
-            off += 3 * (TH >> lev) * (TW >> lev);
-        }
-        const float* Dll = D + off;
-        for (int lev = L; lev >= 3; --lev) {
-            const int rows = TH >> lev, cols = TW >> lev;
-            const int rh = (int)ceil_shift(th, lev), rw = (int)ceil_shift(tw, lev);
-            const int oh = (int)ceil_shift(th, lev - 1), ow = (int)ceil_shift(tw, lev - 1);
-            const float* lin = (lev & 1) ? B : A;     // output of level lev+1
-            float* out = (lev & 1) ? A : B;
-            const int pin = TW >> lev, pout = TW >> (lev - 1);
-            const float* Dh = D + offs[lev];
-            for (int b = t; b < rh * rw; b += NT) {
-                const int i = b / rw, k = b - i * rw;
-                const bool r1 = 2 * i + 1 < oh, c1 = 2 * k + 1 < ow;
-                const int e = i * cols + k;
-                const float ll = (lev == L) ? Dll[e] : lin[i * pin + k];
-                float x00, x01, x10, x11;
-                syn_edge(ll, Dh[e], Dh[rows * cols + e], Dh[2 * rows * cols + e], r1, c1, x00, x01,
-                         x10, x11);
-                const int o = (2 * i) * pout + 2 * k;
-                out[o] = x00;
-                if (c1) out[o + 1] = x01;
-                if (r1) out[o + pout] = x10;
-                if (r1 && c1) out[o + pout + 1] = x11;
-            }
-            __syncthreads();
-        }
-    }
-
     // ---- LL2 of this thread (B2Y x B2X), or LL1 directly when L == 1
     float ll1[B1Y][B1X];
     if (L >= 2) {
         float ll2[B2Y][B2X];
         const int64_t R = (r0 >> 2) + (lr0 >> 2), C = (c0 >> 2) + (lc0 >> 2);
-        if (FULL && L >= 3) {
+        if (L >= 3) {
             // walk the ancestor path: LL_L -> ... -> LL3 (one 2x2 synthesis
             // butterfly per level, keeping the child on the path), then the
-            // level-3 butterfly gives this thread's LL2 entries
+            // level-3 butterfly gives this thread's LL2 entries.  Edge tiles
+            // apply the carry rule at every level (syn_child); the values of
+            // a thread whose block lies outside the region are never stored.
             const int64_t R3 = R >> 1, C3 = C >> 1;
             float ll = in.walk[0];
 #pragma unroll
             for (int jj = 2; jj >= 1; --jj) {
                 const int j = 3 + jj;               // level j -> level j-1 (j = 5, 4)
                 if (j <= L) {
+                    const int64_t Rj = R3 >> (j - 3), Cj = C3 >> (j - 3);
                     const int dy = (int)((R3 >> (j - 4)) & 1), dx = (int)((C3 >> (j - 4)) & 1);
                     const float hl = in.walk[1 + 3 * jj], lh = in.walk[2 + 3 * jj],
                                 hh = in.walk[3 + 3 * jj];
-                    const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
-                    ll = 0.5f * (dx ? base + tt : base - tt);
+                    if (FULL) {
+                        const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
+                        ll = 0.5f * (dx ? base + tt : base - tt);
+                    } else {
+                        const bool r1 = 2 * Rj + 1 < ceil_shift(p.h, j - 1);
+                        const bool c1 = 2 * Cj + 1 < ceil_shift(p.w, j - 1);
+                        ll = syn_child(ll, hl, lh, hh, r1, c1, dy, dx);
+                    }
                 }
             }
             const float hl = in.walk[1], lh = in.walk[2], hh = in.walk[3];   // level 3
             const int dy = (int)(R & 1);
+            const bool r1 = FULL || 2 * R3 + 1 < ceil_shift(p.h, 2);
+            const bool c1 = FULL || 2 * C3 + 1 < ceil_shift(p.w, 2);
 #pragma unroll
             for (int k = 0; k < B2X; ++k) {
                 const int dx = (int)((C + k) & 1);
-                const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
-                ll2[0][k] = 0.5f * (dx ? base + tt : base - tt);
+                if (FULL) {
+                    const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
+                    ll2[0][k] = 0.5f * (dx ? base + tt : base - tt);
+                } else {
+                    ll2[0][k] = syn_child(ll, hl, lh, hh, r1, c1, dy, dx);
+                }
             }
         } else {
 #pragma unroll
@@ -744,10 +691,7 @@ __device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_
                 for (int k = 0; k < B2X; ++k) {
                     const int lr = (lr0 >> 2) + i, lc = (lc0 >> 2) + k;
                     const bool ok = FULL || (lr < th2 && lc < tw2);
-                    if (L >= 3)
-                        ll2[i][k] = ok ? A[lr * (TW / 4) + lc] : 0.0f;
-                    else
-                        ll2[i][k] = ok ? ld1<SL>(llp + (R + i) * lp + C + k) : 0.0f;
+                    ll2[i][k] = ok ? ld1<SL>(llp + (R + i) * lp + C + k) : 0.0f;
                 }
         }
 #pragma unroll

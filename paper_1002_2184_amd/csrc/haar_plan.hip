@@ -111,15 +111,16 @@ __device__ __forceinline__ void walk_units(unsigned n, unsigned* ctr, unsigned* 
 // WB: XCD-contiguous units and write-back stores (WriteBack<S>), so that the
 // partial cache lines that neighbouring tiles of a misaligned image share are
 // merged in L2 instead of being streamed to HBM twice.
+// At least 5 wavefronts per SIMD: the 16-bit analysis kernels sit at the
+// 96-register boundary of that occupancy.
 template <class S, int GY, int GX, bool INV, bool DYN, bool WB>
-__global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __restrict__ items,
+__global__ __launch_bounds__(GY* GX) __attribute__((amdgpu_waves_per_eu(5))) void plan2d_kernel(const PlanItem2D* __restrict__ items,
                                                         const PlanTile2D* __restrict__ tiles,
                                                         unsigned ntiles, unsigned* ctr) {
     constexpr int RX = 16 / S::kBytes;
     using SO = std::conditional_t<WB, WriteBack<S>, S>;   // storage of the outputs
     using G = Geo2D<S, 4, RX, GY, GX>;
-    constexpr int SM_FWD = G::SMEM, SM_INV = G::AN + G::BN + G::QPT * G::NT;
-    __shared__ float sm[SM_FWD > SM_INV ? SM_FWD : SM_INV];
+    __shared__ float sm[G::SMEM];                          // analysis levels 3..L
     __shared__ unsigned s_slot;
     walk_units<DYN, WB>(ntiles, ctr, &s_slot, [&](unsigned unit) {
         const PlanTile2D d = tiles[unit];
@@ -156,11 +157,11 @@ __global__ __launch_bounds__(GY* GX) void plan2d_kernel(const PlanItem2D* __rest
             if (d.full) {
                 In in;
                 inv2d_load<SO, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in);
-                inv2d_body<SO, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in, sm);
+                inv2d_body<SO, S, S, 4, RX, GY, GX, true>(p, 0, d.ty, d.tx, in);
             } else {
                 In in;
                 inv2d_load<SO, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in);
-                inv2d_body<SO, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in, sm);
+                inv2d_body<SO, S, S, 4, RX, GY, GX, false>(p, 0, d.ty, d.tx, in);
             }
         }
     });

@@ -284,9 +284,8 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_edge_kernel(const void* x, vo
     using G = Geo2D<S, 4, RX, GY, GX>;
     using In = InvInT<S, StLds, StLds, 4, RX, GY, GX>;
     constexpr int TH = G::TH, TW = G::TW, NT = G::NT;
-    constexpr int SMF = G::SMEM, SMI = G::AN + G::BN + G::QPT * G::NT;
     __shared__ float buf[TH * TW];           // the tile's packed coefficients (pitch TW)
-    __shared__ float sm[SMF > SMI ? SMF : SMI];
+    __shared__ float sm[G::SMEM];            // analysis levels 3..L
     __shared__ float thr[kMaxShrinkLevels];
     if (threadIdx.x < kMaxShrinkLevels) thr[threadIdx.x] = sh.thr[threadIdx.x];
     const int64_t per = right + bottom;
@@ -334,7 +333,7 @@ __global__ __launch_bounds__(GY* GX) void shrink2d_edge_kernel(const void* x, vo
         {
             In in;
             inv2d_load<S, StLds, StLds, 4, RX, GY, GX, false>(p, 0, 0, 0, in);
-            inv2d_body<S, StLds, StLds, 4, RX, GY, GX, false>(p, 0, 0, 0, in, sm);
+            inv2d_body<S, StLds, StLds, 4, RX, GY, GX, false>(p, 0, 0, 0, in);
         }
         __syncthreads();                     // LDS reuse by the next tile
     }
