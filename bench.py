@@ -23,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -39,11 +40,19 @@ KERNEL_SOURCES = ["paper_1002_2184_amd/csrc/haar_2d.hip", "paper_1002_2184_amd/c
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd2d_inv2d_4096x4096_L5.json")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank lines: edits to comments do not
+    change the kernels, so they do not invalidate a traffic measurement."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln.strip())
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -136,8 +145,8 @@ def write_traffic(fetch_csv: str, write_csv: str, command: str):
             f.write(f"| {k} | {v['fetch_kib_raw']:.0f} | {v['write_kib_raw']:.0f} | "
                     f"{v['hbm_read_bytes'] / 2**20:.2f} | {v['hbm_write_bytes'] / 2**20:.2f} | "
                     f"{v['vs_algorithmic']:.4f} |\n")
-        f.write(f"\nKernel sources sha256[:16] = {kernel_hash()} (bench.py reports traffic only "
-                f"while the sources match).\n")
+        f.write(f"\nKernel sources sha256[:16] = {kernel_hash()}, over the code without comments "
+                f"(bench.py reports traffic only while the code matches).\n")
     print(json.dumps(doc))
 
 

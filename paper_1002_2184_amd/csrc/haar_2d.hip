@@ -8,10 +8,10 @@ namespace haar {
 #define HAAR_MIN_WAVES_2D 1
 #endif
 
-// Tile index -> (item, ty, tx).  Interior launches (EDGE = false) walk the
-// grid of full tiles and run the vector path only; edge launches walk the
-// right column and bottom row of partial tiles, or every tile when the
-// layout is not aligned for vectors (p.vec_ok == 0), on the scalar path.
+// Tile index -> (item, ty, tx).  EDGE = false: the grid of full tiles (vector
+// path); EDGE = true: the right column and bottom row of partial tiles, or
+// every tile when the layout is not aligned for vectors (p.vec_ok == 0), on
+// the scalar path.
 template <bool EDGE>
 __device__ __forceinline__ void tile_coords(const Pass2D& p, int64_t tile, int64_t& item,
                                             int64_t& ty, int64_t& tx) {

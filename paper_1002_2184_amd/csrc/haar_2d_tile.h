@@ -7,15 +7,17 @@
 // Per thread: an RY x RX register block (16 bytes per row: 4 x f32 or
 // 8 x bf16/f16).  Levels 1 and 2 run in registers on 2x2 blocks
 // (Eq. (11)-(12) along the width, then along the height, fused into one
-// butterfly per 2x2 block with the exact factor 1/2 = b00^2); deeper levels
-// of the pass run in LDS on the tile's LL2 region.  The approximation path of
-// the analysis carries compensated FP32 pairs.
+// butterfly per 2x2 block with the exact factor 1/2 = b00^2).  The deeper
+// levels of the analysis run in wavefront shuffles and in LDS on the tile's
+// LL2 or LL3 region; the synthesis derives each thread's LL2 values from
+// their ancestor path, with no LDS.  The approximation path of the analysis
+// carries compensated FP32 pairs.
 //
-// Interior tiles whose rows and band origins are 16-byte aligned take the
-// vector path (FULL = true).  Edge tiles and unaligned layouts take the same
-// code with per-element validity (FULL = false), where the odd-size carry
-// rule applies: at an odd row/column count the last row/column passes
-// unscaled into the approximation.
+// Full tiles of element-aligned layouts take the vector path (FULL = true).
+// Edge tiles and unaligned layouts take the same code with per-element
+// validity (FULL = false), where the odd-size carry rule applies: at an odd
+// row/column count the last row/column passes unscaled into the
+// approximation.
 #pragma once
 
 #include "haar_device.h"
