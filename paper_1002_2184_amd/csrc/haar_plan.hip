@@ -90,9 +90,14 @@ __device__ __forceinline__ void retire(unsigned* ctr) {
 // work-group): work-groups are dealt round-robin to the 8 XCDs, so block b
 // takes unit xcd_tile(b), which gives every XCD one contiguous range of the
 // list; neighbouring tiles of an image then run on one XCD and share its L2.
-template <bool DYN, bool REMAP, class F>
+// ONE: the grid has one work-group per unit; straight-line code without the
+// walk loop, which needs fewer registers.
+template <bool DYN, bool REMAP, bool ONE, class F>
 __device__ __forceinline__ void walk_units(unsigned n, unsigned* ctr, unsigned* s_slot, F&& body) {
-    if constexpr (DYN) {
+    if constexpr (ONE) {
+        const unsigned b = blockIdx.x;
+        if (b < n) body(REMAP ? (unsigned)xcd_tile(b, n) : b);
+    } else if constexpr (DYN) {
         unsigned unit;
         while (claim(ctr, s_slot, n, unit)) {
             body((unsigned)__builtin_amdgcn_readfirstlane((int)unit));
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(GY* GX) __attribute__((amdgpu_waves_per_eu(5))) voi
     using G = Geo2D<S, 4, RX, GY, GX>;
     __shared__ float sm[G::SMEM];                          // analysis levels 3..L
     __shared__ unsigned s_slot;
-    walk_units<DYN, WB>(ntiles, ctr, &s_slot, [&](unsigned unit) {
+    walk_units<DYN, WB, false>(ntiles, ctr, &s_slot, [&](unsigned unit) {
         const PlanTile2D d = tiles[unit];
         const PlanItem2D it = items[d.item];
         Pass2D p{};
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(GY* GX) __attribute__((amdgpu_waves_per_eu(5))) voi
 // ---------------------------------------------------------------------------
 // 1D
 // ---------------------------------------------------------------------------
-template <class S, bool INV, bool DYN>
+template <class S, bool INV, bool DYN, bool ONE>
 __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __restrict__ items,
                                                          const PlanChunk1D* __restrict__ chunks,
                                                          unsigned nunits, unsigned* ctr, float* a32) {
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
     __shared__ float smf[NW * 8];
     __shared__ float stage[kPlanC1];
     __shared__ unsigned s_slot;
-    walk_units<DYN, false>(nunits, ctr, &s_slot, [&](unsigned unit) {
+    walk_units<DYN, false, ONE>(nunits, ctr, &s_slot, [&](unsigned unit) {
         const PlanChunk1D d = chunks[unit];
         const PlanItem1D it = items[d.item];
         Pass1D p{};
@@ -339,8 +344,14 @@ hipError_t launch_plan1d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
         return hipGetLastError();
     };
     const bool dyn = pl->sched == 1;
-    if (pl->inverse) return dyn ? go(plan1d_kernel<S, true, true>) : go(plan1d_kernel<S, true, false>);
-    hipError_t e = dyn ? go(plan1d_kernel<S, false, true>) : go(plan1d_kernel<S, false, false>);
+    // synthesis with one work-group per unit: the straight-line kernel (61
+    // VGPRs against 105) ran the 1024-signal batch in 0.35 ms against 0.47;
+    // the analysis ran slower that way (0.32-0.34 against 0.31 ms)
+    const bool one = pl->sched == 2 && (int64_t)n <= kPlanGridCap;
+    if (pl->inverse)
+        return dyn ? go(plan1d_kernel<S, true, true, false>)
+                   : (one ? go(plan1d_kernel<S, true, false, true>) : go(plan1d_kernel<S, true, false, false>));
+    hipError_t e = dyn ? go(plan1d_kernel<S, false, true, false>) : go(plan1d_kernel<S, false, false, false>);
     if (e != hipSuccess || query_only || pl->deep1.empty()) return e;
     const int32_t* deep = (const int32_t*)((char*)ws + pl->off_deep);
     const unsigned nd = (unsigned)pl->deep1.size();
