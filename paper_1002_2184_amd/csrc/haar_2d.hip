@@ -8,6 +8,7 @@ namespace haar {
 #define HAAR_MIN_WAVES_2D 1
 #endif
 
+
 // Tile index -> (item, ty, tx).  EDGE = false: the grid of full tiles (vector
 // path); EDGE = true: the right column and bottom row of partial tiles, or
 // every tile when the layout is not aligned for vectors (p.vec_ok == 0), on
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_persistent_ke
 // each bound by its own memory latency (measured: 4096 x 4128 FP32 analysis
 // 40 us in two launches, 33 us in one).  Straight-line code without a tile
 // loop also needs fewer registers than the persistent kernels.
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, int MAP>
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, int MAP, bool NTL>
 __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D p, int64_t nedge,
                                                                          int64_t ninterior) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
@@ -129,19 +130,19 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void fwd2d_kernel(Pass2D
     FwdIn<RY, RX> in;
     if (b < nedge) {
         tile_coords<true>(p, b, item, ty, tx);
-        fwd2d_load<SX, RY, RX, GY, GX, false, MAP>(p, item, ty, tx, in);
+        fwd2d_load<SX, RY, RX, GY, GX, false, MAP, NTL>(p, item, ty, tx, in);
         fwd2d_body<SX, SD, SL, RY, RX, GY, GX, false, MAP>(p, item, ty, tx, in, sm);
     } else {
         const int64_t t = b - nedge;
         // (XCD-contiguous order only when the edge blocks leave the round-robin
         // dealing of blocks to XCDs aligned: block b goes to XCD b mod 8)
         tile_coords<false>(p, (p.remap && (nedge & 7) == 0) ? xcd_tile(t, ninterior) : t, item, ty, tx);
-        fwd2d_load<SX, RY, RX, GY, GX, true, MAP>(p, item, ty, tx, in);
+        fwd2d_load<SX, RY, RX, GY, GX, true, MAP, NTL>(p, item, ty, tx, in);
         fwd2d_body<SX, SD, SL, RY, RX, GY, GX, true, MAP>(p, item, ty, tx, in, sm);
     }
 }
 
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX>
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool NTL>
 __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D p, int64_t nedge,
                                                                          int64_t ninterior) {
     using In = InvInT<SX, SD, SL, RY, RX, GY, GX>;
@@ -150,14 +151,14 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D
     In in;
     if (b < nedge) {
         tile_coords<true>(p, b, item, ty, tx);
-        inv2d_load<SX, SD, SL, RY, RX, GY, GX, false>(p, item, ty, tx, in);
+        inv2d_load<SX, SD, SL, RY, RX, GY, GX, false, NTL>(p, item, ty, tx, in);
         inv2d_body<SX, SD, SL, RY, RX, GY, GX, false>(p, item, ty, tx, in);
     } else {
         const int64_t t = b - nedge;
         // (XCD-contiguous order only when the edge blocks leave the round-robin
         // dealing of blocks to XCDs aligned: block b goes to XCD b mod 8)
         tile_coords<false>(p, (p.remap && (nedge & 7) == 0) ? xcd_tile(t, ninterior) : t, item, ty, tx);
-        inv2d_load<SX, SD, SL, RY, RX, GY, GX, true>(p, item, ty, tx, in);
+        inv2d_load<SX, SD, SL, RY, RX, GY, GX, true, NTL>(p, item, ty, tx, in);
         inv2d_body<SX, SD, SL, RY, RX, GY, GX, true>(p, item, ty, tx, in);
     }
 }
@@ -211,12 +212,22 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     if (p.persist == 0 && p.total_tiles <= kMaxGrid) {
         if (p.total_tiles <= 0) return hipSuccess;
         const unsigned grid = (unsigned)p.total_tiles;
-        if (inverse)
-            hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX>), dim3(grid), dim3(GY * GX), 0, s, p,
-                               edge, interior);
-        else
-            hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, MAP>), dim3(grid), dim3(GY * GX), 0,
-                               s, p, edge, interior);
+        // tiles that own whole cache lines read them with nontemporal loads
+        if (inverse) {
+            if (p.ntl)
+                hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, true>), dim3(grid), dim3(GY * GX), 0,
+                                   s, p, edge, interior);
+            else
+                hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, false>), dim3(grid), dim3(GY * GX),
+                                   0, s, p, edge, interior);
+        } else {
+            if (p.ntl)
+                hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, MAP, true>), dim3(grid),
+                                   dim3(GY * GX), 0, s, p, edge, interior);
+            else
+                hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, MAP, false>), dim3(grid),
+                                   dim3(GY * GX), 0, s, p, edge, interior);
+        }
         return hipGetLastError();
     }
     if (interior > 0) {

@@ -158,7 +158,11 @@ __device__ __forceinline__ df shfl_xor_df(df a, int m) {
     return df{__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)};
 }
 
-template <class SX, int RY, int RX, int GY, int GX, bool FULL, int MAP = 0>
+
+// NTL: nontemporal vector loads (launches whose tiles own whole cache
+// lines, p.ntl; a separate kernel, since a run-time choice between two loads
+// that differ only in that hint gets merged into the ordinary one).
+template <class SX, int RY, int RX, int GY, int GX, bool FULL, int MAP = 0, bool NTL = false>
 __device__ __forceinline__ void fwd2d_load(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
                                            FwdIn<RY, RX>& in) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
@@ -174,7 +178,8 @@ __device__ __forceinline__ void fwd2d_load(const Pass2D& p, int64_t item, int64_
         reinterpret_cast<const typename SX::raw*>(p.src) + item * p.src_bstride + r0 * p.src_pitch + c0;
     if (FULL || (lr0 + RY <= th && lc0 + RX <= tw)) {   // whole register block inside
 #pragma unroll
-        for (int r = 0; r < RY; ++r) ld_vec<SX, RX>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0, in.v[r]);
+        for (int r = 0; r < RY; ++r)
+            ld_vec<SX, RX, NTL>(src + (int64_t)(lr0 + r) * p.src_pitch + lc0, in.v[r]);
     } else {
 #pragma unroll
         for (int r = 0; r < RY; ++r)
@@ -517,7 +522,9 @@ struct InvIn {
 template <class SX, class SD, class SL, int RY, int RX, int GY, int GX>
 using InvInT = InvIn<RY / 2, RX / 2, RY / 4, RX / 4>;
 
-template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL>
+// NTL: nontemporal loads of the level-1/2 band vectors (see fwd2d_load); the
+// ancestor-path values, shared by many lanes, stay ordinary loads.
+template <class SX, class SD, class SL, int RY, int RX, int GY, int GX, bool FULL, bool NTL = false>
 __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_t ty, int64_t tx,
                                            InvInT<SX, SD, SL, RY, RX, GY, GX>& in) {
     using G = Geo2D<SX, RY, RX, GY, GX>;
@@ -573,9 +580,9 @@ __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_
 #pragma unroll
         for (int i = 0; i < B1Y; ++i) {
             if (inb) {
-                ld_vec<SD, B1X>(det + (R + i) * dp + ws + C, in.hl1[i]);
-                ld_vec<SD, B1X>(det + (hs + R + i) * dp + C, in.lh1[i]);
-                ld_vec<SD, B1X>(det + (hs + R + i) * dp + ws + C, in.hh1[i]);
+                ld_vec<SD, B1X, NTL>(det + (R + i) * dp + ws + C, in.hl1[i]);
+                ld_vec<SD, B1X, NTL>(det + (hs + R + i) * dp + C, in.lh1[i]);
+                ld_vec<SD, B1X, NTL>(det + (hs + R + i) * dp + ws + C, in.hh1[i]);
             } else {
 #pragma unroll
                 for (int k = 0; k < B1X; ++k) {
@@ -596,9 +603,9 @@ __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_
 #pragma unroll
         for (int i = 0; i < B2Y; ++i) {
             if (inb) {
-                ld_vec<SD, B2X>(det + (R + i) * dp + ws + C, in.hl2[i]);
-                ld_vec<SD, B2X>(det + (hs + R + i) * dp + C, in.lh2[i]);
-                ld_vec<SD, B2X>(det + (hs + R + i) * dp + ws + C, in.hh2[i]);
+                ld_vec<SD, B2X, NTL>(det + (R + i) * dp + ws + C, in.hl2[i]);
+                ld_vec<SD, B2X, NTL>(det + (hs + R + i) * dp + C, in.lh2[i]);
+                ld_vec<SD, B2X, NTL>(det + (hs + R + i) * dp + ws + C, in.hh2[i]);
             } else {
 #pragma unroll
                 for (int k = 0; k < B2X; ++k) {

@@ -127,6 +127,23 @@ static int vec_ok_2d(const Pass2D& p, bool inverse, int ebx, int ebd, int ebl) {
     return aligned(region, ebx) && aligned(p.det, ebd) && aligned(p.ll, ebl) ? 1 : 0;
 }
 
+// Every row piece that a tile reads (region rows, level-1/2 band rows) covers
+// whole 128-byte lines, so no cache line is read by two work-groups and the
+// vector loads can be nontemporal.  Where tiles share lines (rows that start
+// inside a line), ordinary loads let the second reader hit in L2.
+static int own_lines_2d(const Pass2D& p, bool inverse, int ebx, int ebd, int tw) {
+    auto lines = [](const void* base, int64_t pitch, int64_t bstride, int eb) {
+        return aligned(base, 128) && (pitch * eb) % 128 == 0 && (bstride * eb) % 128 == 0;
+    };
+    const void* region = inverse ? (const void*)p.dst : p.src;
+    const int64_t rp = inverse ? p.dst_pitch : p.src_pitch, rb = inverse ? p.dst_bstride : p.src_bstride;
+    const bool ok = lines(region, rp, rb, ebx) && (tw * ebx) % 128 == 0 &&
+                    lines(p.det, p.det_pitch, p.det_bstride, ebd) &&
+                    (ceil_shift_host(p.w, 1) * ebd) % 128 == 0 && (ceil_shift_host(p.w, 2) * ebd) % 128 == 0 &&
+                    ((tw / 4) * ebd) % 128 == 0;
+    return ok ? 1 : 0;
+}
+
 int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch, int dtype,
            bool inverse, hipStream_t s, int cfg_override) {
     const int eb = elem_bytes(dtype);
@@ -180,6 +197,7 @@ int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch
         p.remap = tc.remap;
         p.persist = tc.wg_per_cu > 0 ? (int64_t)tc.wg_per_cu * device_cus() : 0;
         p.vec_ok = vec_ok_2d(p, inverse, ebx, eb, ebl);
+        p.ntl = own_lines_2d(p, inverse, ebx, eb, tc.tw());
         hipError_t e = inverse ? launch_inv2d(p, dtype, pcfg, x_f32, ll_f32, s)
                                : launch_fwd2d(p, dtype, pcfg, x_f32, ll_f32, s);
         if (e != hipSuccess) rc = hip_error(e, inverse ? "inv2d launch" : "fwd2d launch");

@@ -193,15 +193,16 @@ typedef unsigned int u32e __attribute__((aligned(2)));
 // generic pointers.
 #define HAAR_GLOBAL __attribute__((address_space(1)))
 
-template <class S, class T>
+// NT: a nontemporal load, for data that is read once and shares no cache
+// line with another work-group's reads.
+template <class S, class T, bool NT = false>
 __device__ __forceinline__ T ld_s(const T* p) {
     if constexpr (S::kStream) {
         const HAAR_GLOBAL T* g = (const HAAR_GLOBAL T*)p;
-#if HAAR_NT_LOADS
-        return __builtin_nontemporal_load(g);
-#else
-        return *g;
-#endif
+        if constexpr (NT || HAAR_NT_LOADS)
+            return __builtin_nontemporal_load(g);
+        else
+            return *g;
     } else {
         return *p;
     }
@@ -209,32 +210,32 @@ __device__ __forceinline__ T ld_s(const T* p) {
 
 // Load N consecutive elements (N * kBytes in {2, 4, 8, 16}; the pointer
 // needs only element alignment) into floats.
-template <class S, int N>
+template <class S, int N, bool NT = false>
 __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
     constexpr int B = N * S::kBytes;
     static_assert(B == 2 || B == 4 || B == 8 || B == 16, "vector width");
     if constexpr (S::kBytes == 4) {
         if constexpr (N == 4) {
-            const v4f v = ld_s<S>(reinterpret_cast<const v4f*>(p));
+            const v4f v = ld_s<S, v4f, NT>(reinterpret_cast<const v4f*>(p));
             out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
         } else if constexpr (N == 2) {
-            const v2f v = ld_s<S>(reinterpret_cast<const v2f*>(p));
+            const v2f v = ld_s<S, v2f, NT>(reinterpret_cast<const v2f*>(p));
             out[0] = v.x; out[1] = v.y;
         } else {
-            out[0] = ld_s<S>(reinterpret_cast<const float*>(p));
+            out[0] = ld_s<S, float, NT>(reinterpret_cast<const float*>(p));
         }
     } else {
         uint32_t w[B >= 4 ? B / 4 : 1];
         if constexpr (B == 16) {
-            const v4u v = ld_s<S>(reinterpret_cast<const v4u*>(p));
+            const v4u v = ld_s<S, v4u, NT>(reinterpret_cast<const v4u*>(p));
             w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
         } else if constexpr (B == 8) {
-            const v2u v = ld_s<S>(reinterpret_cast<const v2u*>(p));
+            const v2u v = ld_s<S, v2u, NT>(reinterpret_cast<const v2u*>(p));
             w[0] = v.x; w[1] = v.y;
         } else if constexpr (B == 4) {
-            w[0] = ld_s<S>(reinterpret_cast<const u32e*>(p));
+            w[0] = ld_s<S, u32e, NT>(reinterpret_cast<const u32e*>(p));
         } else {
-            out[0] = S::ld(ld_s<S>(p));
+            out[0] = S::ld(ld_s<S, typename S::raw, NT>(p));
             return;
         }
 #pragma unroll

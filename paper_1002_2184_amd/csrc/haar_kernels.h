@@ -22,6 +22,7 @@ struct Pass2D {
     int64_t full_x, full_y;                 // tiles that lie entirely inside the region
     int32_t remap;                          // deal contiguous tile ranges to each XCD
     int64_t persist;                        // interior grid size (0 = one tile per work-group)
+    int32_t ntl;                            // every tile owns whole cache lines: nontemporal loads
 };
 
 // One fused 1D pass: `levels` levels on a length-n region (chunks of C).
