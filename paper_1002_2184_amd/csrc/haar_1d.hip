@@ -14,7 +14,7 @@ namespace haar {
 // covers them all), so the chunk loop runs once and the compiler keeps far
 // fewer values live (synthesis of full deep chunks: 35 VGPRs against 104;
 // 256 x 65 536 FP32, 16 levels: 38.0 -> 31.1 us, analysis 34.6 -> 33.8 us).
-template <class SX, class SD, class SL, int E, int NT, bool FULL, bool ONE = false>
+template <class SX, class SD, class SL, int E, int NT, bool FULL, bool ONE = false, bool NTL = false>
 __global__ __launch_bounds__(NT) void fwd1d_kernel(Pass1D p, int64_t first, int64_t per, int64_t total) {
     using G = Geo1D<SX, E, NT>;
     __shared__ df sm[G::NW];
@@ -23,13 +23,14 @@ __global__ __launch_bounds__(NT) void fwd1d_kernel(Pass1D p, int64_t first, int6
     for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
         const int64_t c = remap ? xcd_tile(b, total) : b;
         const int64_t item = c / per, chunk = first + (c - item * per);
-        fwd1d_chunk<SX, SD, SL, E, NT, FULL>(p, item, chunk, sm, stage);
+        fwd1d_chunk<SX, SD, SL, E, NT, FULL, NTL>(p, item, chunk, sm, stage);
         if (ONE) break;
         if (b + gridDim.x < total) __syncthreads();
     }
 }
 
-template <class SX, class SD, class SL, int E, int NT, bool FULL, bool WALK, bool DEEP = false, bool ONE = false>
+template <class SX, class SD, class SL, int E, int NT, bool FULL, bool WALK, bool DEEP = false, bool ONE = false,
+          bool NTL = false>
 __global__ __launch_bounds__(NT) void inv1d_kernel(Pass1D p, int64_t first, int64_t per, int64_t total) {
     using G = Geo1D<SX, E, NT>;
     __shared__ float sm[G::NW * 8];
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(NT) void inv1d_kernel(Pass1D p, int64_t first, int6
         if (WALK)
             top = walk_down<SD>(reinterpret_cast<const typename SD::raw*>(p.det) + item * p.det_bstride,
                                 p.n, p.levels_total, p.levels, chunk);
-        inv1d_chunk<SX, SD, SL, E, NT, FULL, DEEP>(p, item, chunk, sm, stage, WALK, top);
+        inv1d_chunk<SX, SD, SL, E, NT, FULL, DEEP, NTL>(p, item, chunk, sm, stage, WALK, top);
         if (ONE) break;
         if (b + gridDim.x < total) __syncthreads();
     }
@@ -119,17 +120,29 @@ Chunk1D chunk_config_1d(int index) {
 
 template <class SX, class SD, class SL, int NT, int E>
 static hipError_t launch1d(const Pass1D& p, bool inverse, hipStream_t s) {
+    // full chunks that own whole cache lines read them with nontemporal loads
     if (inverse) {
-        if (p.levels > Log2<E>::v)
+        if (p.levels > Log2<E>::v) {
+            if (p.ntl)
+                return launch_split1d(p, NT * E, NT, inv1d_kernel<SX, SD, SL, E, NT, true, false, true>,
+                                      inv1d_kernel<SX, SD, SL, E, NT, false, false>,
+                                      inv1d_kernel<SX, SD, SL, E, NT, true, false, true, true, true>,
+                                      inv1d_kernel<SX, SD, SL, E, NT, false, false, false, true>, s);
             return launch_split1d(p, NT * E, NT, inv1d_kernel<SX, SD, SL, E, NT, true, false, true>,
                                   inv1d_kernel<SX, SD, SL, E, NT, false, false>,
                                   inv1d_kernel<SX, SD, SL, E, NT, true, false, true, true>,
                                   inv1d_kernel<SX, SD, SL, E, NT, false, false, false, true>, s);
+        }
         return launch_split1d(p, NT * E, NT, inv1d_kernel<SX, SD, SL, E, NT, true, false>,
                               inv1d_kernel<SX, SD, SL, E, NT, false, false>,
                               inv1d_kernel<SX, SD, SL, E, NT, true, false, false, true>,
                               inv1d_kernel<SX, SD, SL, E, NT, false, false, false, true>, s);
     }
+    if (p.ntl)
+        return launch_split1d(p, NT * E, NT, fwd1d_kernel<SX, SD, SL, E, NT, true>,
+                              fwd1d_kernel<SX, SD, SL, E, NT, false>,
+                              fwd1d_kernel<SX, SD, SL, E, NT, true, true, true>,
+                              fwd1d_kernel<SX, SD, SL, E, NT, false, true>, s);
     return launch_split1d(p, NT * E, NT, fwd1d_kernel<SX, SD, SL, E, NT, true>,
                           fwd1d_kernel<SX, SD, SL, E, NT, false>,
                           fwd1d_kernel<SX, SD, SL, E, NT, true, true>,
@@ -210,6 +223,11 @@ hipError_t launch_finish1d(const Pass1D& p, int dtype, int lc, int L, bool src32
 template <class S, int NT, int E>
 static hipError_t walk_t(const Pass1D& p, hipStream_t s) {
     // the walk covers the whole chunk depth, so full chunks are always deep
+    if (p.ntl)
+        return launch_split1d(p, NT * E, NT, inv1d_kernel<S, S, S, E, NT, true, true, true>,
+                              inv1d_kernel<S, S, S, E, NT, false, true>,
+                              inv1d_kernel<S, S, S, E, NT, true, true, true, true, true>,
+                              inv1d_kernel<S, S, S, E, NT, false, true, false, true>, s);
     return launch_split1d(p, NT * E, NT, inv1d_kernel<S, S, S, E, NT, true, true, true>,
                           inv1d_kernel<S, S, S, E, NT, false, true>,
                           inv1d_kernel<S, S, S, E, NT, true, true, true, true>,

@@ -66,7 +66,8 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class SX, int E>
+// NTL: nontemporal loads (chunks that own whole cache lines).
+template <class SX, int E, bool NTL = false>
 __device__ __forceinline__ void ld_chunk_lanes(const typename SX::raw* src, float* stage, float (&x)[E],
                                                int lane, int wv) {
     constexpr int VEC = 16 / SX::kBytes, NV = E / VEC;
@@ -74,7 +75,7 @@ __device__ __forceinline__ void ld_chunk_lanes(const typename SX::raw* src, floa
     float* st = stage + wv * 64 * E;
     float v[NV][VEC];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) ld_vec<SX, VEC>(ws + (q * 64 + lane) * VEC, v[q]);
+    for (int q = 0; q < NV; ++q) ld_vec<SX, VEC, NTL>(ws + (q * 64 + lane) * VEC, v[q]);
 #pragma unroll
     for (int q = 0; q < NV; ++q)
 #pragma unroll
@@ -186,7 +187,7 @@ __device__ __forceinline__ void ld_approx(float (&a)[E], int L, const typename S
     }
 }
 
-template <class SX, class SD, class SL, int E, int NT, bool FULL>
+template <class SX, class SD, class SL, int E, int NT, bool FULL, bool NTL = false>
 __device__ __forceinline__ void fwd1d_chunk(const Pass1D& p, int64_t item, int64_t chunk, df* sm,
                                             float* stage) {
     using G = Geo1D<SX, E, NT>;
@@ -201,7 +202,7 @@ __device__ __forceinline__ void fwd1d_chunk(const Pass1D& p, int64_t item, int64
 
     float x[E];
     if constexpr (FULL) {
-        ld_chunk_lanes<SX, E>(src, stage, x, lane, wv);
+        ld_chunk_lanes<SX, E, NTL>(src, stage, x, lane, wv);
     } else {
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = (t * E + e < cl) ? ld1<SX>(src + t * E + e) : 0.0f;
@@ -287,7 +288,7 @@ __device__ __forceinline__ void fwd1d_chunk(const Pass1D& p, int64_t item, int64
 // loads are issued as straight-line code (a lane that holds no value of a
 // wavefront level reads its group's value: same address, same cache line), so
 // that no branch separates them and they overlap in one memory round trip.
-template <class SX, class SD, class SL, int E, int NT, bool FULL, bool DEEP = false>
+template <class SX, class SD, class SL, int E, int NT, bool FULL, bool DEEP = false, bool NTL = false>
 __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64_t chunk, float* sm,
                                             float* stage, bool has_top = false, float top = 0.0f) {
     static_assert(!DEEP || FULL, "the straight-line loads need a full chunk");
@@ -316,7 +317,7 @@ __device__ __forceinline__ void inv1d_chunk(const Pass1D& p, int64_t item, int64
             if (cnt >= VECD) {
 #pragma unroll
                 for (int q = 0; q < (E / 2 + VECD - 1) / VECD; ++q)
-                    if (q * VECD < cnt) ld_vec<SD, VECD>(dp + q * VECD, o + q * VECD);
+                    if (q * VECD < cnt) ld_vec<SD, VECD, NTL>(dp + q * VECD, o + q * VECD);
             } else {
 #pragma unroll
                 for (int m = 0; m < E / 2; ++m)

@@ -262,6 +262,18 @@ static Pass1D chunk_pass(const void* in, void* out, int64_t N, int lv, int64_t b
     return p;
 }
 
+// Every chunk's region span and level-1/2 band spans cover whole 128-byte
+// lines (see own_lines_2d): nontemporal loads.
+static int own_lines_1d(const Pass1D& p, bool inverse, int ebx, int ebd, int64_t chunk) {
+    const void* region = inverse ? (const void*)p.dst : p.src;
+    const int64_t rb = inverse ? p.dst_bstride : p.src_bstride;
+    const bool ok = aligned(region, 128) && (rb * ebx) % 128 == 0 && (chunk * ebx) % 128 == 0 &&
+                    aligned(p.det, 128) && (p.det_bstride * ebd) % 128 == 0 &&
+                    (ceil_shift_host(p.n, 1) * ebd) % 128 == 0 && (ceil_shift_host(p.n, 2) * ebd) % 128 == 0 &&
+                    ((chunk / 4) * ebd) % 128 == 0;
+    return ok ? 1 : 0;
+}
+
 int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype, bool inverse,
            hipStream_t s, int cfg_override) {
     const int eb = elem_bytes(dtype);
@@ -285,6 +297,7 @@ int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype
             p.ll_bstride = m;
         }
         p.vec_ok = vec_ok_1d(p, false, eb, eb, a32 ? 4 : eb);
+        p.ntl = own_lines_1d(p, false, eb, eb, cc.chunk());
         hipError_t e = launch_fwd1d(p, dtype, cfg, false, a32 != nullptr, s);
         if (e == hipSuccess) e = launch_finish1d(p, dtype, depth, L, a32 != nullptr, s);
         int rc = e == hipSuccess ? HAAR_OK : hip_error(e, "fwd1d launch");
@@ -298,6 +311,7 @@ int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype
         Pass1D p = chunk_pass(in, out, N, depth, batch, true, cc);
         p.levels_total = L;
         p.vec_ok = vec_ok_1d(p, true, eb, eb, eb);
+        p.ntl = own_lines_1d(p, true, eb, eb, cc.chunk());
         hipError_t e = launch_inv1d_walk(p, dtype, cfg, s);
         return e == hipSuccess ? HAAR_OK : hip_error(e, "inv1d launch");
     }
@@ -336,6 +350,7 @@ int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype
         p.chunks_per_item = (r.n + cc.chunk() - 1) / cc.chunk();
         p.total_chunks = p.chunks_per_item * batch;
         p.vec_ok = vec_ok_1d(p, inverse, ebx, eb, ll_f32 ? 4 : eb);
+        p.ntl = own_lines_1d(p, inverse, ebx, eb, cc.chunk());
         hipError_t e = inverse ? launch_inv1d(p, dtype, cfg, x_f32, ll_f32, s)
                                : launch_fwd1d(p, dtype, cfg, x_f32, ll_f32, s);
         if (e != hipSuccess) rc = hip_error(e, inverse ? "inv1d launch" : "fwd1d launch");

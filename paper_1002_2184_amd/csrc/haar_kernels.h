@@ -37,6 +37,7 @@ struct Pass1D {
     int64_t chunks_per_item, total_chunks;
     int32_t remap;                          // deal contiguous chunk ranges to each XCD
     int32_t levels_total;                   // synthesis with walk: all levels of the transform
+    int32_t ntl;                            // every chunk owns whole cache lines: nontemporal loads
 };
 
 // Tile shapes of the 2D kernels (per storage width): rows/cols per thread

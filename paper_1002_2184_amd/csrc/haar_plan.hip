@@ -175,7 +175,8 @@ __global__ __launch_bounds__(GY* GX) __attribute__((amdgpu_waves_per_eu(5))) voi
 // ---------------------------------------------------------------------------
 // 1D
 // ---------------------------------------------------------------------------
-template <class S, bool INV, bool DYN, bool ONE>
+// NTL: every item's chunks own whole cache lines (nontemporal loads).
+template <class S, bool INV, bool DYN, bool ONE, bool NTL>
 __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __restrict__ items,
                                                          const PlanChunk1D* __restrict__ chunks,
                                                          unsigned nunits, unsigned* ctr, float* a32) {
@@ -201,13 +202,13 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
             if (it.levels > it.chunk_levels) {
                 p.ll = a32 + it.a32;
                 if (full)
-                    fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd, stage);
+                    fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, true, NTL>(p, 0, d.chunk, smd, stage);
                 else
                     fwd1d_chunk<S, S, StF32, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd, stage);
             } else {
                 p.ll = it.out;
                 if (full)
-                    fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smd, stage);
+                    fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, true, NTL>(p, 0, d.chunk, smd, stage);
                 else
                     fwd1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smd, stage);
             }
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(kPlanNT1) void plan1d_kernel(const PlanItem1D* __re
                                                   it.levels, kPlanLogC1, d.chunk)
                                    : 0.0f;
             if (full)
-                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, true>(p, 0, d.chunk, smf, stage, deep, top);
+                inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, true, false, NTL>(p, 0, d.chunk, smf, stage, deep, top);
             else
                 inv1d_chunk<S, S, S, kPlanE1, kPlanNT1, false>(p, 0, d.chunk, smf, stage, deep, top);
         }
@@ -265,6 +266,7 @@ struct haar_plan {
     size_t off_items = 0, off_units = 0, off_deep = 0, off_a32 = 0, ws_bytes = 0;
     int64_t nunits = 0;
     int grid = 0;
+    bool ntl1 = false;                 // 1D: every item's chunks own whole cache lines
     bool uploaded = false;
     const void* uploaded_to = nullptr;
 };
@@ -349,9 +351,13 @@ hipError_t launch_plan1d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
     // the analysis ran slower that way (0.32-0.34 against 0.31 ms)
     const bool one = pl->sched == 2 && (int64_t)n <= kPlanGridCap;
     if (pl->inverse)
-        return dyn ? go(plan1d_kernel<S, true, true, false>)
-                   : (one ? go(plan1d_kernel<S, true, false, true>) : go(plan1d_kernel<S, true, false, false>));
-    hipError_t e = dyn ? go(plan1d_kernel<S, false, true, false>) : go(plan1d_kernel<S, false, false, false>);
+        return dyn ? go(plan1d_kernel<S, true, true, false, false>)
+                   : one ? (pl->ntl1 ? go(plan1d_kernel<S, true, false, true, true>)
+                                     : go(plan1d_kernel<S, true, false, true, false>))
+                         : go(plan1d_kernel<S, true, false, false, false>);
+    hipError_t e = dyn ? go(plan1d_kernel<S, false, true, false, false>)
+                       : pl->ntl1 ? go(plan1d_kernel<S, false, false, false, true>)
+                                  : go(plan1d_kernel<S, false, false, false, false>);
     if (e != hipSuccess || query_only || pl->deep1.empty()) return e;
     const int32_t* deep = (const int32_t*)((char*)ws + pl->off_deep);
     const unsigned nd = (unsigned)pl->deep1.size();
@@ -513,8 +519,13 @@ int haar_plan_create_1d(const haar_item_1d* items, int64_t count, int32_t dtype,
     std::stable_sort(order.begin(), order.end(),
                      [&](int64_t a, int64_t b) { return items[a].length > items[b].length; });
     int64_t a32_floats = 0;
+    pl->ntl1 = true;
     for (int64_t oi = 0; oi < count; ++oi) {
         const haar_item_1d& it = items[order[oi]];
+        // chunk spans of the signal and of its level-1/2 bands on whole lines
+        pl->ntl1 = pl->ntl1 && aligned(it.in, 128) && aligned(it.out, 128) && (it.length * eb) % 128 == 0 &&
+                   (ceil_shift_host(it.length, 1) * eb) % 128 == 0 &&
+                   (ceil_shift_host(it.length, 2) * eb) % 128 == 0;
         PlanItem1D pi{};
         pi.in = it.in;
         pi.out = it.out;
