@@ -35,8 +35,11 @@ H = W = 4096
 LEVELS = 5
 PEAK_GBPS = 8000.0          # MI355X HBM3E, 8 TB/s
 SETS = 16
+# the code of the timed launches: their kernels and the host code that picks
+# their tile shape, load hints and block order
 KERNEL_SOURCES = ["paper_1002_2184_amd/csrc/haar_2d.hip", "paper_1002_2184_amd/csrc/haar_2d_tile.h",
-                  "paper_1002_2184_amd/csrc/haar_device.h"]
+                  "paper_1002_2184_amd/csrc/haar_device.h", "paper_1002_2184_amd/csrc/haar_api.hip",
+                  "paper_1002_2184_amd/csrc/haar_tune.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd2d_inv2d_4096x4096_L5.json")
 
 
@@ -187,6 +190,22 @@ def _timed(fn, reps, warm, stream):
     return a.elapsed_time(b) / reps
 
 
+def _graphed(fn, stream):
+    """fn captured once into a HIP graph (after one eager warm-up on a side
+    stream); returns the replay callable."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        fn()
+        with torch.cuda.graph(g, stream=side):
+            fn()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    return g.replay
+
+
 def suite():
     """The other workloads, each beside the plain FP32 transform on this GPU.
     Prints one JSON line per workload (not the benchmark contract line)."""
@@ -232,6 +251,7 @@ def suite():
     total = sum(v.numel() for v in xs)
     plan = PL.Plan1D(xs, ys, levels)
     ms_plan = _timed(plan.execute, 20, 3, st)
+    ms_plan_graph = _timed(_graphed(plan.execute, st), 20, 3, st)
 
     def loop():
         for v, w, lv in zip(xs, ys, levels):
@@ -243,6 +263,8 @@ def suite():
     print(json.dumps({"workload": "1d-batched-uneven-1024x2^[10,20]-fulldepth fwd",
                       "elements": int(total), "ms_plan": round(ms_plan, 4),
                       "gbps_plan": round(2 * total * 4 / (ms_plan * 1e-3) / 1e9, 1),
+                      "ms_plan_graph": round(ms_plan_graph, 4),
+                      "gbps_plan_graph": round(2 * total * 4 / (ms_plan_graph * 1e-3) / 1e9, 1),
                       "ms_per_signal_loop": round(ms_loop, 3),
                       "gbps_plain_same_bytes_65536x16": round(2 * flat.numel() * 4 / (ms_plain * 1e-3) / 1e9, 1)}),
           flush=True)
@@ -313,9 +335,12 @@ def suite():
             pf.execute()
             pb.execute()
         ms5 = _timed(fb, 10, 2, st)
+        ms5g = _timed(_graphed(fb, st), 10, 2, st)
         nel = sum(v.numel() for v in xs)
         res[f"ms_{name}"] = round(ms5, 4)
         res[f"gbps_{name}"] = round(4 * nel * xs[0].element_size() / (ms5 * 1e-3) / 1e9, 1)
+        res[f"ms_{name}_graph"] = round(ms5g, 4)
+        res[f"gbps_{name}_graph"] = round(4 * nel * xs[0].element_size() / (ms5g * 1e-3) / 1e9, 1)
         res[f"elements_per_s_{name}"] = round(2 * nel / (ms5 * 1e-3) / 1e9, 2)
         del xs, gs, ys, zs, pf, pb
         torch.cuda.empty_cache()
@@ -453,8 +478,9 @@ def volumes():
         del vs, cs
 
 
-def cpu_baseline(x_np, budget_s: float):
-    """The FP64 oracle (fwd + inv of the same image) on this host's cores."""
+def _oracle_rate(x_np, budget_s: float, max_reps: int):
+    """Repeated fwd + inv of the image through the FP64 oracle: (GB/s, reps,
+    seconds, threads), GB/s counting the algorithmic bytes of the FP32 step."""
     import numpy as np
     import oracle
     xw = x_np.astype(np.float64)
@@ -465,12 +491,48 @@ def cpu_baseline(x_np, budget_s: float):
         orc.inv_2d(y, LEVELS)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 20:
+        if el >= budget_s or reps >= max_reps:
             break
-    alg = 4.0 * H * W * 4 * reps
-    return {"value": round(alg / el / 1e9, 4), "unit": "GB/s", "cores": orc.num_threads(),
-            "kind": "oracle",
-            "sample": f"{reps} x (5-level fwd + inv of the 4096x4096 image), FP64, {el:.1f} s"}
+    return 4.0 * H * W * 4 * reps / el / 1e9, reps, el, orc.num_threads()
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x_np, budget_s: float):
+    """The FP64 oracle (fwd + inv of the same image) on all of this host's
+    cores, and on one core (a child process with OMP_NUM_THREADS=1)."""
+    import subprocess
+    gbps, reps, el, thr = _oracle_rate(x_np, budget_s, 20)
+    out = {"value": round(gbps, 4), "unit": "GB/s", "cores": thr, "kind": "oracle",
+           "sample": f"{reps} x (5-level fwd + inv of the 4096x4096 image), FP64, {el:.1f} s",
+           "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-one-core", str(budget_s)],
+                       capture_output=True, text=True, env=env, timeout=300)
+    try:
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        out["one_core"] = {"value": one["value"], "unit": "GB/s", "cores": one["cores"],
+                           "sample": one["sample"]}
+    except (ValueError, IndexError, KeyError):
+        out["one_core"] = None
+    return out
+
+
+def cpu_one_core(budget_s: float):
+    """The one-core leg of the CPU baseline (run with OMP_NUM_THREADS=1)."""
+    from workloads import generators as G
+    gbps, reps, el, thr = _oracle_rate(G.config2(H, W), budget_s, 4)
+    print(json.dumps({"value": round(gbps, 4), "cores": thr,
+                      "sample": f"{reps} x (5-level fwd + inv of the 4096x4096 image), FP64, {el:.1f} s"}))
 
 
 def main():
@@ -490,7 +552,12 @@ def main():
                     help="measure the other workloads (1D latency, batched, autograd, BF16) and exit")
     ap.add_argument("--volumes", action="store_true",
                     help="measure only the 3D volume workloads of the suite and exit")
+    ap.add_argument("--cpu-one-core", type=float, metavar="BUDGET_S",
+                    help="internal: the one-core leg of the CPU baseline")
     args = ap.parse_args()
+    if args.cpu_one_core is not None:
+        cpu_one_core(args.cpu_one_core)
+        return
     if args.suite:
         suite()
         return

@@ -32,8 +32,14 @@
  *   orthonormal; it equals the usual Haar transform when 2^L divides the
  *   size).
  * Types.  dtype selects the STORAGE type of input and output (haar_dtype).
- *   Arithmetic is always FP32 (the approximation path carries a compensated
- *   FP32 pair); reduced-precision results are rounded to nearest even.
+ *   Reduced-precision results are rounded to nearest even.  Arithmetic:
+ *   the 1D and 2D transforms, the fused shrinkage and the direct bank
+ *   compute in FP32 (the approximation path of the analysis carries a
+ *   compensated FP32 pair); the 3D transforms compute in FP64 on the device
+ *   (the approximation grows by 2^(3/2) per level, and FP64 keeps every sum
+ *   exact at the cost of unpacked-FP32 issue rate; the last synthesis level
+ *   into 16-bit storage runs in FP32); haar_l1_grad_2d computes the
+ *   transform in FP32 and sums the loss in FP64.
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
  *   stream).  Calls are asynchronous: they enqueue kernels and return; they
  *   never synchronise.  Device faults surface at the caller's next
@@ -131,7 +137,8 @@ int haar_inv_2d(const void* y, void* x, int64_t height, int64_t width,
  * is high-pass along a set of axes lies on the high side of those axes.
  * Odd counts carry their last sample unscaled on each axis.  Three levels
  * are fused per pass; deeper transforms allocate stream-ordered scratch of
- * 8 bytes per element of the level-3 LLL region (twice). */
+ * 8 bytes per element of the level-3 LLL region (twice).  Arithmetic is
+ * FP64 on the device (samples are widened, every output is rounded once). */
 int haar_fwd_3d(const void* x, void* y, int64_t depth, int64_t height,
                 int64_t width, int32_t levels, int64_t batch, int32_t dtype,
                 void* stream);
@@ -333,6 +340,15 @@ int haar_tune_candidates_2d(int32_t dtype);
 const char* haar_tune_candidate_name(int32_t dtype, int32_t index);
 /* Force candidate `index` (or -1 to restore table/default choice) for 2D. */
 int haar_force_config_2d(int32_t dtype, int32_t index);
+/* Number of 1D chunk candidates: index -> (threads, samples per thread,
+ * XCD-contiguous chunk order): 0: 256 x 16 (the default beyond 2048
+ * samples), 1: 1024 x 16, 2: 64 x 16, 3: 128 x 16, 4: 256 x 16 in plain
+ * block order. */
+int haar_tune_candidates_1d(void);
+/* Force 1D chunk candidate `index` (or -1 to restore the table/default
+ * choice) for plain 1D calls of storage `dtype`; HAAR_ERR_UNSUPPORTED for an
+ * index outside [-1, haar_tune_candidates_1d()). */
+int haar_force_config_1d(int32_t dtype, int32_t index);
 
 /* ------------------------------------------------------------------------
  * Diagnostics.

@@ -72,6 +72,8 @@ _SIGS = {
     "haar_tune_candidates_2d": ([_I32], ctypes.c_int),
     "haar_tune_candidate_name": ([_I32, _I32], ctypes.c_char_p),
     "haar_force_config_2d": ([_I32, _I32], ctypes.c_int),
+    "haar_force_config_1d": ([_I32, _I32], ctypes.c_int),
+    "haar_tune_candidates_1d": ([], ctypes.c_int),
     "haar_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "haar_last_error": ([], ctypes.c_char_p),
     "haar_version": ([], ctypes.c_char_p),
@@ -234,6 +236,14 @@ def haar_tune_candidate_name(dtype, index):
 
 def haar_force_config_2d(dtype, index):
     return lib().haar_force_config_2d(dtype, index)
+
+
+def haar_force_config_1d(dtype, index):
+    return lib().haar_force_config_1d(dtype, index)
+
+
+def haar_tune_candidates_1d():
+    return lib().haar_tune_candidates_1d()
 
 
 def haar_status_string(status):

@@ -25,6 +25,7 @@ namespace haar {
 static std::mutex g_mu;
 static std::map<std::string, int> g_table;
 static int g_force_2d[3] = {-1, -1, -1};
+static int g_force_1d[3] = {-1, -1, -1};
 
 static const char* dtype_name(int d) { return d == 0 ? "f32" : (d == 1 ? "bf16" : "f16"); }
 
@@ -63,6 +64,7 @@ int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels, 
 int choose_config_1d(int dtype, bool inverse, int64_t n, int levels) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        if (dtype >= 0 && dtype < 3 && g_force_1d[dtype] >= 0) return g_force_1d[dtype];
         auto it = g_table.find(key_1d(dtype, inverse, n, levels));
         if (it != g_table.end()) return it->second;
     }
@@ -147,6 +149,17 @@ int haar_force_config_2d(int32_t dtype, int32_t index) {
     g_force_2d[dtype] = index;
     return HAAR_OK;
 }
+
+int haar_force_config_1d(int32_t dtype, int32_t index) {
+    if (dtype < 0 || dtype > 2) return set_error(HAAR_ERR_DTYPE, "dtype %d is not a haar_dtype", dtype);
+    if (index < -1 || index >= num_chunk_configs_1d())
+        return set_error(HAAR_ERR_UNSUPPORTED, "no 1D chunk configuration %d", index);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_force_1d[dtype] = index;
+    return HAAR_OK;
+}
+
+int haar_tune_candidates_1d(void) { return num_chunk_configs_1d(); }
 
 int haar_tune_2d(int32_t dtype, int32_t inverse, int64_t height, int64_t width, int32_t levels,
                  int64_t batch, void* scratch, size_t scratch_bytes, void* stream,

@@ -131,7 +131,11 @@ def check_lowp_coeffs(gpu64, ref64, x_rms, dt, bands, what="", band_gate=False):
         if band_gate:
             lim = LOWP_TOL * max(peak, floor)
             assert err <= lim, f"{what} band {key}: max err {err:.3e} > 1e-2 * max|band| = {lim:.3e}"
+        # the floor: the same measures for the correctly rounded oracle itself
+        fl = float(np.max(np.abs(rounded[sl] - r)))
         table[key] = {"max_err_over_band_peak": err / max(peak, floor),
                       "rms_err_over_band_rms": rms(g - r) / max(br, floor),
-                      "max_err_over_band_rms": err / max(br, floor)}
+                      "max_err_over_band_rms": err / max(br, floor),
+                      "floor_max_err_over_band_peak": fl / max(peak, floor),
+                      "floor_max_err_over_band_rms": fl / max(br, floor)}
     return table

@@ -31,10 +31,10 @@ def T():
     return transform
 
 
-@pytest.mark.parametrize("dt,n,L", _cases(), ids=lambda v: str(v))
-def test_fwd_inv_1d(T, dt, n, L):
-    batch = 2
-    rng = np.random.default_rng(n * 31 + L + dt)
+def _check_fwd_inv(T, dt, n, L, batch=2, seed=0, what=""):
+    """Analysis of a seeded signal batch, synthesis of the oracle's stored
+    coefficients and the round trip, each against the oracle."""
+    rng = np.random.default_rng(seed)
     xs = G.to_storage(rng.standard_normal((batch, n)) * 2.0 + 0.5, dt)
     xw = G.widen(xs, dt)
     ref = oracle.fwd_1d(xw, L)
@@ -43,19 +43,24 @@ def test_fwd_inv_1d(T, dt, n, L):
     for b in range(batch):
         r = rms(xw[b])
         if dt == G.F32:
-            check_signal(yw[b], ref[b], r, dt, f"fwd n={n} L={L} item {b}")
+            check_signal(yw[b], ref[b], r, dt, f"{what} fwd n={n} L={L} item {b}")
         else:
-            check_lowp_coeffs(yw[b], ref[b], r, dt, band_views(n, L), f"fwd n={n} L={L} item {b}")
+            check_lowp_coeffs(yw[b], ref[b], r, dt, band_views(n, L), f"{what} fwd n={n} L={L} item {b}")
     cs = G.to_storage(ref, dt)
     cw = G.widen(cs, dt)
     xref = oracle.inv_1d(cw, L)
     xr = G.widen(to_host(T.inv1d(to_device(cs, dt), L), dt), dt)
     for b in range(batch):
         chk = check_signal if dt == G.F32 else check_lowp_signal
-        chk(xr[b], xref[b], rms(cw[b]), dt, f"inv n={n} L={L} item {b}")
+        chk(xr[b], xref[b], rms(cw[b]), dt, f"{what} inv n={n} L={L} item {b}")
     x2 = G.widen(to_host(T.inv1d(y, L), dt), dt)
     for b in range(batch):
-        check_roundtrip(x2[b], xw[b], dt, f"round trip n={n} L={L} item {b}")
+        check_roundtrip(x2[b], xw[b], dt, f"{what} round trip n={n} L={L} item {b}")
+
+
+@pytest.mark.parametrize("dt,n,L", _cases(), ids=lambda v: str(v))
+def test_fwd_inv_1d(T, dt, n, L):
+    _check_fwd_inv(T, dt, n, L, seed=n * 31 + L + dt)
 
 
 def test_constant_signal_exact(T):
@@ -97,11 +102,30 @@ def test_config3_signals_sample(T):
         check_signal(xr, xw, rms(xw), G.F32, f"config3 round trip n={n}")
 
 
-def test_chunk_configs_agree(T):
-    from paper_1002_2184_amd import transform
-    import torch
-    x = torch.randn(3, 50000, device="cuda")
-    ref = oracle.fwd_1d(x.cpu().numpy().astype(np.float64), 15)
-    y = transform.fwd1d(x, 15).cpu().numpy().astype(np.float64)
-    for b in range(3):
-        check_signal(y[b], ref[b], rms(ref[b]), G.F32, "default chunks")
+# Chunk shapes a tuning table or haar_tune_1d can select (threads x samples
+# per thread): 0: 256 x 16 (default), 1: 1024 x 16, 2: 64 x 16, 3: 128 x 16,
+# 4: 256 x 16 without the XCD-contiguous chunk order.
+CHUNKS = {0: 4096, 1: 16384, 2: 1024, 3: 2048, 4: 4096}
+
+
+def _chunk_cases():
+    out = []
+    for cfg, c in CHUNKS.items():
+        depth = c.bit_length() - 1
+        for dt in DTYPES:
+            out += [(cfg, dt, c, depth, "one chunk, all its levels"),
+                    (cfg, dt, 3 * c + 777, 5, "ragged last chunk"),
+                    (cfg, dt, 3 * c + 777, int(np.ceil(np.log2(3 * c + 777))), "ragged, full depth"),
+                    (cfg, dt, 65536, 16, "deep: finish kernel / ancestor walk")]
+    return out
+
+
+@pytest.mark.parametrize("cfg,dt,n,L,what", _chunk_cases(), ids=lambda v: str(v))
+def test_chunk_configs(T, cfg, dt, n, L, what):
+    """Every chunk configuration, forced for the plain calls, against the oracle."""
+    from paper_1002_2184_amd import _abi
+    assert _abi.haar_force_config_1d(dt, cfg) == 0
+    try:
+        _check_fwd_inv(T, dt, n, L, seed=1000 + 7 * cfg + n + L, what=f"chunk config {cfg} ({what})")
+    finally:
+        assert _abi.haar_force_config_1d(dt, -1) == 0

@@ -137,7 +137,7 @@ def _sigs(dt, lengths, seed):
     return [G.to_storage(rng.standard_normal(n) + 0.3, dt) for n in lengths]
 
 
-@pytest.mark.parametrize("dt", [G.F32, G.BF16])
+@pytest.mark.parametrize("dt", [G.F32, G.BF16, G.F16])
 def test_plan1d_full_depth_matches_oracle(P, dt):
     import torch
     xs = _sigs(dt, LENGTHS_1D, seed=5 + dt)
@@ -160,19 +160,22 @@ def test_plan1d_full_depth_matches_oracle(P, dt):
                 # items deeper than 12 levels keep their level-12 values in FP32
                 # between the two kernels: every coefficient within 1 ulp
                 check_lowp_coeffs(yw, ref, rms(xw), dt, band_views(x.size, L), f"plan1d fwd n={x.size}")
-    if dt != G.F32:
-        return
+    # the synthesis plan on the oracle's stored coefficients (items deeper than
+    # 12 levels walk their ancestor path through the 16-bit coefficients)
     cs = [G.to_storage(oracle.fwd_1d(G.widen(x, dt), L), dt) for x, L in zip(xs, levels)]
     cd = [to_device(c, dt) for c in cs]
     zd = [torch.empty_like(c) for c in cd]
     iplan = P.Plan1D(cd, zd, levels, inverse=True)
+    chk = check_signal if dt == G.F32 else check_lowp_signal
     for rep in range(2):
+        for z in zd:
+            z.fill_(float("nan"))
         iplan.execute()
         torch.cuda.synchronize()
         for c, z, L in zip(cs, zd, levels):
             cw = G.widen(c, dt)
-            check_signal(G.widen(to_host(z, dt), dt), oracle.inv_1d(cw, L), rms(cw), dt,
-                         f"plan1d inv n={c.size} rep {rep}")
+            chk(G.widen(to_host(z, dt), dt), oracle.inv_1d(cw, L), rms(cw), dt,
+                f"plan1d inv n={c.size} L={L} rep {rep}")
 
 
 def test_plan1d_schedules(P):
