@@ -206,6 +206,23 @@ int haar_l1_grad_2d(const void* x, void* grad_x, double* loss, int64_t height,
                     int64_t width, int32_t levels, int64_t batch,
                     int32_t dtype, void* stream);
 
+/* The same training step without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc.  Arguments, results and
+ * errors are those of haar_l1_grad_2d; the tile loss partials live in a
+ * static device array of the library (2^19 doubles = 4 MiB, held on every
+ * GPU the library runs on until the process ends) instead of stream-ordered
+ * scratch.  One partial per tile: tiles are 32 rows x 128 columns (FP32) or
+ * 32 x 256 (BF16/FP16), counting partial tiles at the right and bottom
+ * edges, times batch; a call needing more than 2^19 returns
+ * HAAR_ERR_WORKSPACE before enqueueing anything.  Calls that overlap in time
+ * on one GPU share the array and race: serialise them (one stream, or
+ * events).  The first call on a device looks the array's address up with
+ * hipGetSymbolAddress (no allocation); nothing is enqueued for that. */
+int haar_l1_grad_2d_noalloc(const void* x, void* grad_x, double* loss,
+                            int64_t height, int64_t width, int32_t levels,
+                            int64_t batch, int32_t dtype, void* stream);
+
 /* ------------------------------------------------------------------------
  * The direct ("original") filter bank, for comparison with the fast bank.
  * Analysis per level (Fig. 1 / Fig. 2, taps of Eq. (8)-(9)): convolve the

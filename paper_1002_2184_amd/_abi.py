@@ -47,6 +47,7 @@ _SIGS = {
     "haar_fwd_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_inv_2d": ([_VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_l1_grad_2d": ([_VP, _VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
+    "haar_l1_grad_2d_noalloc": ([_VP, _VP, _VP, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_fwd_3d": ([_VP, _VP, _I64, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_inv_3d": ([_VP, _VP, _I64, _I64, _I64, _I32, _I64, _I32, _VP], ctypes.c_int),
     "haar_shrink_1d": ([_VP, _VP, _I64, _I32, _I64, _I32, _I32, _FP, _VP], ctypes.c_int),
@@ -124,6 +125,10 @@ def haar_inv_2d(y, x, height, width, levels, batch, dtype, stream=0):
 
 def haar_l1_grad_2d(x, grad_x, loss, height, width, levels, batch, dtype, stream=0):
     return lib().haar_l1_grad_2d(x, grad_x, loss, height, width, levels, batch, dtype, stream)
+
+
+def haar_l1_grad_2d_noalloc(x, grad_x, loss, height, width, levels, batch, dtype, stream=0):
+    return lib().haar_l1_grad_2d_noalloc(x, grad_x, loss, height, width, levels, batch, dtype, stream)
 
 
 def haar_fwd_3d(x, y, depth, height, width, levels, batch, dtype, stream=0):

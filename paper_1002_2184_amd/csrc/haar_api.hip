@@ -523,6 +523,29 @@ int haar_l1_grad_2d(const void* x, void* grad_x, double* loss, int64_t height, i
     return run_l1_grad_2d(x, grad_x, loss, height, width, levels, batch, dtype, (hipStream_t)stream);
 }
 
+int haar_l1_grad_2d_noalloc(const void* x, void* grad_x, double* loss, int64_t height, int64_t width,
+                            int32_t levels, int64_t batch, int32_t dtype, void* stream) {
+    if (height < 1 || width < 1)
+        return set_error(HAAR_ERR_SHAPE, "height %lld / width %lld < 1", (long long)height,
+                         (long long)width);
+    if (height > INT64_MAX / width) return set_error(HAAR_ERR_SHAPE, "height * width overflows");
+    bool nothing = false;
+    int rc = check_common(x, grad_x, height * width, levels, haar_max_levels_2d(height, width), batch,
+                          dtype, &nothing);
+    if (rc != HAAR_OK || nothing) return rc;
+    if (!loss) return set_error(HAAR_ERR_NULL, "loss is NULL");
+    if (levels < 1 || levels > kMaxShrinkLevels2D)
+        return set_error(HAAR_ERR_UNSUPPORTED, "the fused loss gradient runs 1..%d levels", kMaxShrinkLevels2D);
+    const int64_t parts = l1_grad_partials(height, width, batch, dtype);
+    if (parts > kStaticLossPartials)
+        return set_error(HAAR_ERR_WORKSPACE,
+                         "the call needs %lld tile loss partials; the static scratch holds %lld "
+                         "(use haar_l1_grad_2d, or fewer or smaller items per call)",
+                         (long long)parts, (long long)kStaticLossPartials);
+    if (rc = fault_injected(); rc != HAAR_OK) return rc;
+    return run_l1_grad_2d_static(x, grad_x, loss, height, width, levels, batch, dtype, (hipStream_t)stream);
+}
+
 size_t haar_direct_workspace_size(int64_t length, int64_t batch) {
     if (length < 1 || batch < 0) return 0;
     return direct_workspace_floats(length, batch) * sizeof(float);

@@ -50,6 +50,13 @@ int run_shrink_1d(const void* in, void* out, int64_t n, int L, int64_t batch, in
 // loss of each item (levels <= 5).
 int run_l1_grad_2d(const void* in, void* out, double* loss, int64_t h, int64_t w, int L, int64_t batch,
                    int dtype, hipStream_t s);
+// The same with the loss partials in the library's static device array of
+// kStaticLossPartials doubles (no allocation); l1_grad_partials() is the
+// number of partials (tiles) a call needs.
+constexpr int64_t kStaticLossPartials = (int64_t)1 << 19;
+int64_t l1_grad_partials(int64_t h, int64_t w, int64_t batch, int dtype);
+int run_l1_grad_2d_static(const void* in, void* out, double* loss, int64_t h, int64_t w, int L,
+                          int64_t batch, int dtype, hipStream_t s);
 // Direct (convolve-then-decimate) structure, for comparison with the fast bank.
 size_t direct_workspace_floats(int64_t n, int64_t batch);
 int run_direct_1d(const void* in, void* out, int64_t n, int L, int64_t batch, int dtype, bool inverse,

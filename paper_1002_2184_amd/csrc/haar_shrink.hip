@@ -31,8 +31,12 @@
 // place); only the small deep levels cross LDS (2D: the tile's LL2 region,
 // run by one wavefront; 1D: the levels across wavefronts, on one thread).
 #include "haar_1d_chunk.h"
+#include "haar.h"
 #include "haar_2d_tile.h"
 #include "haar_internal.h"
+
+#include <atomic>
+#include <mutex>
 
 namespace haar {
 
@@ -638,33 +642,105 @@ int run_shrink_2d(const void* in, void* out, int64_t h, int64_t w, int L, int64_
     return e == hipSuccess ? 0 : hip_error(e, "shrink2d launch");
 }
 
+// Loss partials of the training step without allocation
+// (haar_l1_grad_2d_noalloc): one double per tile in a file-scope device
+// array.  Every GPU the library runs on holds its own copy until the process
+// ends.  In host code the array's name is a host-side stand-in, not a device
+// address: host code uses only the address hipGetSymbolAddress returns for
+// the current device, kept per device by static_partials().  Every tile
+// writes its own partial before the reduction reads it, so nothing in the
+// array has to start at zero; calls that overlap in time on one GPU share it
+// and race.
+static __device__ __align__(256) double scratch[kStaticLossPartials];
+
+constexpr int kMaxScratchDevices = 64;
+static std::atomic<double*> g_scratch_dev[kMaxScratchDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+static int static_partials(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return set_error(HAAR_ERR_UNSUPPORTED, "device %d beyond the %d devices the static scratch serves", dev,
+                         kMaxScratchDevices);
+    double* p = g_scratch_dev[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_dev[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            void* addr = nullptr;
+            e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress (static loss partials)");
+            if (!addr) return set_error(HAAR_ERR_HIP, "hipGetSymbolAddress returned NULL for the loss partials");
+            p = static_cast<double*>(addr);
+            g_scratch_dev[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return 0;
+}
+
+template <class S>
+static int64_t l1_grad_parts_s(int64_t h, int64_t w, int64_t batch) {
+    const ShrinkGrid2D g = shrink_grid2d<S>(h, w);
+    return (g.per_full() + g.per_edge()) * batch;
+}
+
+int64_t l1_grad_partials(int64_t h, int64_t w, int64_t batch, int dtype) {
+    return dtype == 0 ? l1_grad_parts_s<StF32>(h, w, batch) : l1_grad_parts_s<StBF16>(h, w, batch);
+}
+
+// partial = nullptr: the loss partials live in stream-ordered scratch
+// (hipMallocAsync / hipFreeAsync on s); otherwise in the given device array
+// of at least l1_grad_partials() doubles.
 template <class S>
 static int l1_grad_2d_s(const void* in, void* out, double* loss, int64_t h, int64_t w, int L, int64_t batch,
-                        hipStream_t s) {
+                        double* partial, hipStream_t s) {
     const ShrinkGrid2D g = shrink_grid2d<S>(h, w);
     const int64_t nfull = g.per_full() * batch, nparts = nfull + g.per_edge() * batch;
     ShrinkArgs a{};
-    hipError_t e = hipMallocAsync((void**)&a.partial, (size_t)nparts * sizeof(double), s);
-    if (e != hipSuccess) return hip_error(e, "hipMallocAsync (loss partials)");
-    e = launch_shrink2d<S, kOpL1>(in, out, h, w, L, batch, a, s);
+    const bool own = partial == nullptr;
+    if (own) {
+        hipError_t e = hipMallocAsync((void**)&a.partial, (size_t)nparts * sizeof(double), s);
+        if (e != hipSuccess) return hip_error(e, "hipMallocAsync (loss partials)");
+    } else {
+        a.partial = partial;
+    }
+    hipError_t e = launch_shrink2d<S, kOpL1>(in, out, h, w, L, batch, a, s);
     if (e == hipSuccess) {
         const unsigned grid = (unsigned)(batch < kMaxGridShrink ? batch : kMaxGridShrink);
         hipLaunchKernelGGL(l1_loss_reduce_kernel, dim3(grid), dim3(256), 0, s, a.partial, loss, batch,
                            g.per_full(), g.per_edge(), nfull);
         e = hipGetLastError();
     }
-    const hipError_t ef = hipFreeAsync(a.partial, s);
+    const hipError_t ef = own ? hipFreeAsync(a.partial, s) : hipSuccess;
     if (e != hipSuccess) return hip_error(e, "l1 gradient launch");
     return ef == hipSuccess ? 0 : hip_error(ef, "hipFreeAsync");
 }
 
+static int l1_grad_2d_dtype(const void* in, void* out, double* loss, int64_t h, int64_t w, int L,
+                            int64_t batch, int dtype, double* partial, hipStream_t s) {
+    switch (dtype) {
+        case 0: return l1_grad_2d_s<StF32>(in, out, loss, h, w, L, batch, partial, s);
+        case 1: return l1_grad_2d_s<StBF16>(in, out, loss, h, w, L, batch, partial, s);
+        default: return l1_grad_2d_s<StF16>(in, out, loss, h, w, L, batch, partial, s);
+    }
+}
+
 int run_l1_grad_2d(const void* in, void* out, double* loss, int64_t h, int64_t w, int L, int64_t batch,
                    int dtype, hipStream_t s) {
-    switch (dtype) {
-        case 0: return l1_grad_2d_s<StF32>(in, out, loss, h, w, L, batch, s);
-        case 1: return l1_grad_2d_s<StBF16>(in, out, loss, h, w, L, batch, s);
-        default: return l1_grad_2d_s<StF16>(in, out, loss, h, w, L, batch, s);
-    }
+    return l1_grad_2d_dtype(in, out, loss, h, w, L, batch, dtype, nullptr, s);
+}
+
+int run_l1_grad_2d_static(const void* in, void* out, double* loss, int64_t h, int64_t w, int L,
+                          int64_t batch, int dtype, hipStream_t s) {
+    double* partial = nullptr;
+    const int rc = static_partials(&partial);
+    if (rc != 0) return rc;
+    return l1_grad_2d_dtype(in, out, loss, h, w, L, batch, dtype, partial, s);
 }
 
 }  // namespace haar

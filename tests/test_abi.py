@@ -96,6 +96,11 @@ X, Y = 0x10000000, 0x20000000     # fake, non-overlapping device addresses (neve
     (lambda a: a.haar_l1_grad_2d(X, Y, 0x30000000, 8, 8, 4, 1, 0, 0), 4),           # levels > log2
     (lambda a: a.haar_l1_grad_2d(X, Y, 0, 64, 64, 2, 1, 0, 0), 1),                  # no loss array
     (lambda a: a.haar_l1_grad_2d(X, X + 8, 0x30000000, 64, 64, 2, 1, 0, 0), 5),     # overlap
+    (lambda a: a.haar_l1_grad_2d_noalloc(X, Y, 0x30000000, 64, 64, 6, 1, 0, 0), 9),  # beyond one tile
+    (lambda a: a.haar_l1_grad_2d_noalloc(X, Y, 0x30000000, 8, 8, 4, 1, 0, 0), 4),    # levels > log2
+    (lambda a: a.haar_l1_grad_2d_noalloc(X, Y, 0, 64, 64, 2, 1, 0, 0), 1),           # no loss array
+    (lambda a: a.haar_l1_grad_2d_noalloc(X, X + 8, 0x30000000, 64, 64, 2, 1, 0, 0), 5),  # overlap
+    (lambda a: a.haar_l1_grad_2d_noalloc(X, Y, 0x30000000, 64, 64, 2, 1, 7, 0), 2),  # dtype
 ])
 def test_validation_codes(abi, call, code):
     assert call(abi) == code
@@ -110,6 +115,27 @@ def test_overlap_detects_tail(abi, monkeypatch):
     # fault hook stops the call before anything is enqueued (fake pointers)
     monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")
     assert abi.haar_fwd_2d(X, X + 128, 8, 8, 1, 1, 1, 0) == 7
+
+
+# Fake device pointers far enough apart for multi-GiB shapes (validation only).
+FAR_X, FAR_Y, FAR_LOSS = 1 << 40, 1 << 42, 1 << 44
+
+
+@pytest.mark.parametrize("dt,tile", [(0, 32 * 128), (1, 32 * 256), (2, 32 * 256)])
+def test_l1_grad_noalloc_limit(abi, monkeypatch, dt, tile):
+    """The static loss-partial array holds 2^19 tiles: one more is refused
+    before any HIP call; exactly the limit passes validation (the fault hook
+    then stops it before anything is enqueued)."""
+    limit = 1 << 19
+    # one tile per item, then the limit plus one
+    assert abi.haar_l1_grad_2d_noalloc(FAR_X, FAR_Y, FAR_LOSS, 32, tile // 32, 5, limit + 1, dt, 0) == 6
+    assert "static scratch" in abi.haar_last_error()
+    # ragged items: a 33 x (W + 1) image covers 4 tiles (2 x 2 with the edges)
+    w = tile // 32 + 1
+    assert abi.haar_l1_grad_2d_noalloc(FAR_X, FAR_Y, FAR_LOSS, 33, w, 5, limit // 4 + 1, dt, 0) == 6
+    monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")
+    assert abi.haar_l1_grad_2d_noalloc(FAR_X, FAR_Y, FAR_LOSS, 32, tile // 32, 5, limit, dt, 0) == 7
+    assert abi.haar_l1_grad_2d_noalloc(FAR_X, FAR_Y, FAR_LOSS, 33, w, 5, limit // 4, dt, 0) == 7
 
 
 def test_shrink_accepts_infinite_threshold(abi, monkeypatch):
