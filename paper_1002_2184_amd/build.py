@@ -48,15 +48,18 @@ def _stale() -> bool:
     return any(os.path.getmtime(d) > t for d in deps)
 
 
-def build(force: bool = True, jobs: int = 8, verbose: bool = False, defines=(), out: str = LIB) -> str:
-    """Compile and link; `defines` adds -D flags, `out` redirects the library."""
-    if not force and not _stale() and out == LIB and not defines:
+def build(force: bool = True, jobs: int = 8, verbose: bool = False, defines=(), out: str = LIB,
+          extra_flags=(), link_flags=()) -> str:
+    """Compile and link; `defines` adds -D flags, `out` redirects the library,
+    `extra_flags` / `link_flags` go to every compile / the link (the tests'
+    host-sanitizer build uses them)."""
+    if not force and not _stale() and out == LIB and not defines and not extra_flags:
         return LIB
     tmp = tempfile.mkdtemp(prefix="haarbuild_")
     try:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
-            cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", src, "-o", obj]
+            cmd = [HIPCC, *FLAGS, *extra_flags, *[f"-D{d}" for d in defines], "-c", src, "-o", obj]
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
                 raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
@@ -67,7 +70,7 @@ def build(force: bool = True, jobs: int = 8, verbose: bool = False, defines=(), 
         with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
             objs = list(ex.map(compile_one, sources()))
         out_tmp = out + f".tmp{os.getpid()}"
-        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs]
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_flags, "-o", out_tmp, *objs]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed:\n{r.stderr}")

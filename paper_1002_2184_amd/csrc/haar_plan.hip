@@ -301,10 +301,14 @@ constexpr int64_t kPlanGridCap = (int64_t)1 << 22;
 int unit_grid(const haar_plan* pl, unsigned n, int resident);
 
 // launch helpers -------------------------------------------------------------
+// Address of a table inside the workspace; a grid query (haar_plan_info)
+// passes no workspace, and then no address is formed.
+static inline char* ws_at(void* ws, int64_t off) { return ws ? (char*)ws + off : nullptr; }
+
 template <class S>
 hipError_t launch_plan2d(const haar_plan* pl, void* ws, hipStream_t s, bool query_only, int* grid) {
-    const PlanItem2D* items = (const PlanItem2D*)((char*)ws + pl->off_items);
-    const PlanTile2D* tiles = (const PlanTile2D*)((char*)ws + pl->off_units);
+    const PlanItem2D* items = (const PlanItem2D*)ws_at(ws, pl->off_items);
+    const PlanTile2D* tiles = (const PlanTile2D*)ws_at(ws, pl->off_units);
     unsigned* ctr = (unsigned*)ws;
     const unsigned n = (unsigned)pl->nunits;
     auto go = [&](auto kernel, int threads) -> hipError_t {
@@ -333,10 +337,10 @@ hipError_t launch_plan2d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
 
 template <class S>
 hipError_t launch_plan1d(const haar_plan* pl, void* ws, hipStream_t s, bool query_only, int* grid) {
-    const PlanItem1D* items = (const PlanItem1D*)((char*)ws + pl->off_items);
-    const PlanChunk1D* chunks = (const PlanChunk1D*)((char*)ws + pl->off_units);
+    const PlanItem1D* items = (const PlanItem1D*)ws_at(ws, pl->off_items);
+    const PlanChunk1D* chunks = (const PlanChunk1D*)ws_at(ws, pl->off_units);
     unsigned* ctr = (unsigned*)ws;
-    float* a32 = (float*)((char*)ws + pl->off_a32);
+    float* a32 = (float*)ws_at(ws, pl->off_a32);
     const unsigned n = (unsigned)pl->nunits;
     auto go = [&](auto kernel) -> hipError_t {
         const int g = unit_grid(pl, n, grid_for(kernel, kPlanNT1));
@@ -359,7 +363,7 @@ hipError_t launch_plan1d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
                        : pl->ntl1 ? go(plan1d_kernel<S, false, false, false, true>)
                                   : go(plan1d_kernel<S, false, false, false, false>);
     if (e != hipSuccess || query_only || pl->deep1.empty()) return e;
-    const int32_t* deep = (const int32_t*)((char*)ws + pl->off_deep);
+    const int32_t* deep = (const int32_t*)ws_at(ws, pl->off_deep);
     const unsigned nd = (unsigned)pl->deep1.size();
     hipLaunchKernelGGL(plan1d_finish_kernel<S>, dim3(nd), dim3(256), 0, s, items, deep, nd, a32);
     return hipGetLastError();
