@@ -166,36 +166,42 @@ __global__ __launch_bounds__(GY* GX, HAAR_MIN_WAVES_2D) void inv2d_kernel(Pass2D
 // ---------------------------------------------------------------------------
 // Tile-shape table and launchers
 // ---------------------------------------------------------------------------
-// Index -> (GY, GX, XCD remap, work-groups per CU, analysis thread map);
-// RY = 4 and RX = 16 bytes / element size.  Work-groups per CU = 0: one tile
+// Index -> (RY, GY, GX, XCD remap, work-groups per CU, analysis thread map);
+// RX = 16 bytes / element size: a thread holds RY rows of one 16-byte
+// vector.  Work-groups per CU = 0: one tile
 // per work-group; k > 0: a persistent interior grid of k work-groups per
 // compute unit.  Map 1: wavefront-local analysis; map 2: two-row
 // wavefronts (see thread_rc).
-#define HAAR_2D_TILES(X)      \
-    X(0, 8, 32, 0, 0, 0)      \
-    X(1, 8, 64, 0, 0, 0)      \
-    X(2, 8, 32, 0, 4, 0)      \
-    X(3, 8, 64, 0, 2, 0)      \
-    X(4, 8, 32, 0, 2, 0)      \
-    X(5, 8, 32, 1, 0, 0)      \
-    X(6, 8, 16, 0, 8, 0)      \
-    X(7, 16, 16, 1, 0, 0)     \
-    X(8, 8, 64, 0, 0, 1)      \
-    X(9, 8, 32, 0, 0, 1)      \
-    X(10, 8, 16, 0, 0, 1)     \
-    X(11, 8, 8, 0, 0, 1)      \
-    X(12, 8, 16, 1, 0, 1)     \
-    X(13, 8, 8, 1, 0, 1)      \
-    X(14, 8, 64, 0, 0, 2)
+#define HAAR_2D_TILES(X)         \
+    X(0, 4, 8, 32, 0, 0, 0)      \
+    X(1, 4, 8, 64, 0, 0, 0)      \
+    X(2, 4, 8, 32, 0, 4, 0)      \
+    X(3, 4, 8, 64, 0, 2, 0)      \
+    X(4, 4, 8, 32, 0, 2, 0)      \
+    X(5, 4, 8, 32, 1, 0, 0)      \
+    X(6, 4, 8, 16, 0, 8, 0)      \
+    X(7, 4, 16, 16, 1, 0, 0)     \
+    X(8, 4, 8, 64, 0, 0, 1)      \
+    X(9, 4, 8, 32, 0, 0, 1)      \
+    X(10, 4, 8, 16, 0, 0, 1)     \
+    X(11, 4, 8, 8, 0, 0, 1)      \
+    X(12, 4, 8, 16, 1, 0, 1)     \
+    X(13, 4, 8, 8, 1, 0, 1)      \
+    X(14, 4, 8, 64, 0, 0, 2)     \
+    X(15, 8, 4, 64, 0, 0, 0)     \
+    X(16, 8, 4, 32, 0, 0, 0)     \
+    X(17, 8, 8, 64, 0, 0, 0)     \
+    X(18, 8, 4, 256, 0, 0, 0)    \
+    X(19, 8, 4, 128, 0, 0, 0)
 
-int num_tile_configs_2d(int) { return 15; }
+int num_tile_configs_2d(int) { return 20; }
 
 Tile2D tile_config_2d(int elem_bytes, int index) {
     const int rx = 16 / elem_bytes;
     switch (index) {
-#define X(I, GY_, GX_, RM_, WPC_, MAP_) \
-    case I:                             \
-        return Tile2D{4, rx, GY_, GX_, RM_, WPC_, MAP_};
+#define X(I, RY_, GY_, GX_, RM_, WPC_, MAP_) \
+    case I:                                  \
+        return Tile2D{RY_, rx, GY_, GX_, RM_, WPC_, MAP_};
         HAAR_2D_TILES(X)
 #undef X
         default:
@@ -203,7 +209,7 @@ Tile2D tile_config_2d(int elem_bytes, int index) {
     }
 }
 
-template <class SX, class SD, class SL, int GY, int GX, bool PIPE, int MAP = 0>
+template <class SX, class SD, class SL, int GY, int GX, bool PIPE, int MAP = 0, int RY = 4>
 static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     constexpr int RX = 16 / SX::kBytes;
     constexpr int64_t kMaxGrid = 1 << 20;
@@ -215,17 +221,17 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
         // tiles that own whole cache lines read them with nontemporal loads
         if (inverse) {
             if (p.ntl)
-                hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, true>), dim3(grid), dim3(GY * GX), 0,
+                hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, RY, RX, GY, GX, true>), dim3(grid), dim3(GY * GX), 0,
                                    s, p, edge, interior);
             else
-                hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, 4, RX, GY, GX, false>), dim3(grid), dim3(GY * GX),
+                hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, RY, RX, GY, GX, false>), dim3(grid), dim3(GY * GX),
                                    0, s, p, edge, interior);
         } else {
             if (p.ntl)
-                hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, MAP, true>), dim3(grid),
+                hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, RY, RX, GY, GX, MAP, true>), dim3(grid),
                                    dim3(GY * GX), 0, s, p, edge, interior);
             else
-                hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, 4, RX, GY, GX, MAP, false>), dim3(grid),
+                hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, RY, RX, GY, GX, MAP, false>), dim3(grid),
                                    dim3(GY * GX), 0, s, p, edge, interior);
         }
         return hipGetLastError();
@@ -234,10 +240,10 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
         const int64_t cap = p.persist > 0 ? p.persist : kMaxGrid;
         const unsigned grid = (unsigned)(interior < cap ? interior : cap);
         if (inverse)
-            hipLaunchKernelGGL((inv2d_persistent_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE>), dim3(grid),
+            hipLaunchKernelGGL((inv2d_persistent_kernel<SX, SD, SL, RY, RX, GY, GX, false, PIPE>), dim3(grid),
                                dim3(GY * GX), 0, s, p, interior);
         else
-            hipLaunchKernelGGL((fwd2d_persistent_kernel<SX, SD, SL, 4, RX, GY, GX, false, PIPE, MAP>),
+            hipLaunchKernelGGL((fwd2d_persistent_kernel<SX, SD, SL, RY, RX, GY, GX, false, PIPE, MAP>),
                                dim3(grid), dim3(GY * GX), 0, s, p, interior);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -245,10 +251,10 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     if (edge > 0) {
         const unsigned grid = (unsigned)(edge < kMaxGrid ? edge : kMaxGrid);
         if (inverse)
-            hipLaunchKernelGGL((inv2d_persistent_kernel<SX, SD, SL, 4, RX, GY, GX, true, false>), dim3(grid),
+            hipLaunchKernelGGL((inv2d_persistent_kernel<SX, SD, SL, RY, RX, GY, GX, true, false>), dim3(grid),
                                dim3(GY * GX), 0, s, p, edge);
         else
-            hipLaunchKernelGGL((fwd2d_persistent_kernel<SX, SD, SL, 4, RX, GY, GX, true, false, MAP>),
+            hipLaunchKernelGGL((fwd2d_persistent_kernel<SX, SD, SL, RY, RX, GY, GX, true, false, MAP>),
                                dim3(grid), dim3(GY * GX), 0, s, p, edge);
         return hipGetLastError();
     }
@@ -258,9 +264,9 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
 template <class S>
 static hipError_t dispatch2d(const Pass2D& p, int cfg, bool inverse, hipStream_t s) {
     switch (cfg) {
-#define X(I, GY_, GX_, RM_, WPC_, MAP_) \
-    case I:                             \
-        return launch2d<S, S, S, GY_, GX_, (WPC_ > 0), MAP_>(p, inverse, s);
+#define X(I, RY_, GY_, GX_, RM_, WPC_, MAP_) \
+    case I:                                  \
+        return launch2d<S, S, S, GY_, GX_, (WPC_ > 0), MAP_, RY_>(p, inverse, s);
         HAAR_2D_TILES(X)
 #undef X
         default:

@@ -117,7 +117,7 @@ struct Geo2D {
     static constexpr int AN = (TH / 4) * (TW / 4);   // LDS buffer A: LL2 region
     static constexpr int BN = (TH / 8) * (TW / 8);   // LDS buffer B: LL3 region
     static constexpr int SMEM = 2 * AN + 2 * BN;     // floats (hi + lo each)
-    static_assert(RY == 4 && RX * SX::kBytes == 16, "register block is 4 rows x 16 bytes");
+    static_assert((RY == 4 || RY == 8) && RX * SX::kBytes == 16, "register block is 4 or 8 rows x 16 bytes");
     static_assert(TH % 32 == 0 && TW % 32 == 0, "tile must hold whole 32x32 blocks");
 };
 
@@ -396,7 +396,52 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
     float* Blo = Bhi + G::BN;
     int rh = (th + 3) >> 2, rw = (tw + 3) >> 2;   // local region size at level 2
     int first = 3;                                // first level of the single-wave phase
-    if constexpr (FULL && ((GX == 32 && MAP == 0) || MAP == 2)) {
+    if constexpr (FULL && RY == 8 && MAP == 0) {
+        // Level 3 without LDS: a thread holds LL2 rows 2 rg and 2 rg + 1 of
+        // B2X columns.  With B2X = 2 (16-bit data) the 2x2 block of LL2 is the
+        // thread's own; with B2X = 1 (FP32) the partner column is in lane ^ 1
+        // (column groups are lane-contiguous), so even lanes hold the block.
+        const int lane = t & 63;
+        df x00, x01, x10, x11;
+        bool active;
+        int k3;                                   // level-3 column in the tile
+        if constexpr (B2X == 1) {
+            x00 = a2[0][0];
+            x10 = a2[1][0];
+            x01 = shfl_xor_df(a2[0][0], 1);
+            x11 = shfl_xor_df(a2[1][0], 1);
+            active = (lane & 1) == 0;
+            k3 = cg >> 1;
+        } else {
+            static_assert(B2X == 2, "16-byte rows hold 1 or 2 LL2 columns");
+            x00 = a2[0][0];
+            x01 = a2[0][1];
+            x10 = a2[1][0];
+            x11 = a2[1][1];
+            active = true;
+            k3 = cg;
+        }
+        if (active) {
+            df ll;
+            float hl, lh, hh;
+            ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
+            const int64_t hs = ceil_shift(p.h, 3), ws = ceil_shift(p.w, 3);
+            const int64_t R = (r0 >> 3) + rg, C = (c0 >> 3) + k3;
+            st1<SD>(det + R * dp + ws + C, hl);
+            st1<SD>(det + (hs + R) * dp + C, lh);
+            st1<SD>(det + (hs + R) * dp + ws + C, hh);
+            if (L == 3) {
+                st1<SL>(llp + R * lp + C, df_round(ll));
+            } else {
+                Bhi[rg * (TW / 8) + k3] = ll.hi;
+                Blo[rg * (TW / 8) + k3] = ll.lo;
+            }
+        }
+        if (L == 3) return;
+        rh = TH / 8;
+        rw = TW / 8;
+        first = 4;
+    } else if constexpr (FULL && RY == 4 && ((GX == 32 && MAP == 0) || MAP == 2)) {
         // Level 3 inside each wavefront: a wave holds LL2 rows 2q (lanes
         // 0-31) and 2q+1 (lanes 32-63) of 32 column groups (q = w with 32
         // column groups, w / 2 with the two-row map), so every 2x2 block of
@@ -679,18 +724,24 @@ __device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_
                     }
                 }
             }
-            const float hl = in.walk[1], lh = in.walk[2], hh = in.walk[3];   // level 3
-            const int dy = (int)(R & 1);
+            // level 3: the thread's LL2 rows (one, or the two children rows
+            // of its LL3 coefficient when RY = 8) and columns
+            static_assert(B2Y <= 2 && B2X <= 2, "one LL3 coefficient per thread");
+            const float hl = in.walk[1], lh = in.walk[2], hh = in.walk[3];
             const bool r1 = FULL || 2 * R3 + 1 < ceil_shift(p.h, 2);
             const bool c1 = FULL || 2 * C3 + 1 < ceil_shift(p.w, 2);
 #pragma unroll
-            for (int k = 0; k < B2X; ++k) {
-                const int dx = (int)((C + k) & 1);
-                if (FULL) {
-                    const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
-                    ll2[0][k] = 0.5f * (dx ? base + tt : base - tt);
-                } else {
-                    ll2[0][k] = syn_child(ll, hl, lh, hh, r1, c1, dy, dx);
+            for (int i = 0; i < B2Y; ++i) {
+                const int dy = (int)((R + i) & 1);
+#pragma unroll
+                for (int k = 0; k < B2X; ++k) {
+                    const int dx = (int)((C + k) & 1);
+                    if (FULL) {
+                        const float base = dy ? ll + lh : ll - lh, tt = dy ? hl + hh : hl - hh;
+                        ll2[i][k] = 0.5f * (dx ? base + tt : base - tt);
+                    } else {
+                        ll2[i][k] = syn_child(ll, hl, lh, hh, r1, c1, dy, dx);
+                    }
                 }
             }
         } else {
