@@ -153,6 +153,162 @@ def write_traffic(fetch_csv: str, write_csv: str, command: str):
     print(json.dumps(doc))
 
 
+# Counter probes of the other workloads: (kind) -> what the probe dispatches.
+PMC_KINDS = {
+    "bf16_4096": "fwd2d / inv2d kernels, 4096x4096 BF16, 5 levels, 16 rotating sets",
+    "plans_cfg5": "2D plans of the 512 uneven images, 4 levels, fwd and bwd, in BF16 and in FP32",
+    "plans_cfg3": "1D plans of the 1024 uneven sine-mix signals, full depth, fwd and inv, FP32",
+}
+
+
+def _alg_file(kind: str) -> str:
+    return os.path.join(ROOT, "gpurun_out", f"pmc_{kind}_alg.json")
+
+
+def pmc_probe_kind(kind: str):
+    """Dispatches for the counter passes of one of PMC_KINDS: a 64 MiB device
+    copy (the calibration reference), then 4 launches of each kernel of the
+    workload.  Writes the algorithmic bytes of one dispatch of each kernel
+    class to gpurun_out/pmc_<kind>_alg.json for the summary."""
+    import numpy as np
+    import torch
+    from paper_1002_2184_amd import plan as PL
+    from paper_1002_2184_amd import transform as T
+    from workloads import generators as G
+    dev = torch.device("cuda", 0)
+    ref = torch.empty(H * W, dtype=torch.float32, device=dev)
+    ref2 = torch.empty_like(ref)
+    for _ in range(4):
+        ref2.copy_(ref)
+    torch.cuda.synchronize()
+    alg = {}
+    if kind == "bf16_4096":
+        x0 = torch.from_numpy(G.config2(H, W)).to(dev).to(torch.bfloat16)
+        xs = [x0.clone() for _ in range(SETS)]
+        ys = [torch.empty_like(x0) for _ in range(SETS)]
+        zs = [torch.empty_like(x0) for _ in range(SETS)]
+        for k in range(4):
+            T.fwd2d(xs[k], LEVELS, out=ys[k])
+            T.inv2d(ys[k], LEVELS, out=zs[k])
+        alg = {"fwd2d bf16": 2 * H * W * 2, "inv2d bf16": 2 * H * W * 2}
+    elif kind == "plans_cfg5":
+        imgs, grads = G.config5()
+        for name, dt in (("bf16", torch.bfloat16), ("f32", torch.float32)):
+            if dt == torch.bfloat16:
+                xs = [torch.from_numpy(a.view(np.int16)).to(dev).view(torch.bfloat16) for a in imgs]
+                gs = [torch.from_numpy(a.view(np.int16)).to(dev).view(torch.bfloat16) for a in grads]
+            else:
+                xs = [torch.from_numpy(G.bf16_bits_to_f32(a)).to(dev) for a in imgs]
+                gs = [torch.from_numpy(G.bf16_bits_to_f32(a)).to(dev) for a in grads]
+            ys = [torch.empty_like(v) for v in xs]
+            zs = [torch.empty_like(v) for v in gs]
+            pf = PL.Plan2D(xs, ys, 4)
+            pb = PL.Plan2D(gs, zs, 4, inverse=True)
+            for _ in range(4):
+                pf.execute()
+                pb.execute()
+            torch.cuda.synchronize()
+            nb = 2 * sum(v.numel() for v in xs) * xs[0].element_size()
+            alg[f"plan2d fwd {name}"] = nb
+            alg[f"plan2d inv {name}"] = nb
+            del xs, gs, ys, zs, pf, pb
+            torch.cuda.empty_cache()
+    elif kind == "plans_cfg3":
+        sigs = G.config3()
+        levels = [int(np.log2(v.size)) for v in sigs]
+        xs = [torch.from_numpy(v).to(dev) for v in sigs]
+        ys = [torch.empty_like(v) for v in xs]
+        zs = [torch.empty_like(v) for v in xs]
+        pf = PL.Plan1D(xs, ys, levels)
+        pi = PL.Plan1D(ys, zs, levels, inverse=True)
+        for _ in range(4):
+            pf.execute()
+            pi.execute()
+        nb = 2 * sum(v.numel() for v in xs) * 4
+        alg = {"plan1d fwd f32": nb, "plan1d inv f32": nb,
+               "finish1d f32": 0}
+    else:
+        raise SystemExit(f"unknown counter probe {kind!r}; one of {sorted(PMC_KINDS)}")
+    torch.cuda.synchronize()
+    os.makedirs(os.path.dirname(_alg_file(kind)), exist_ok=True)
+    with open(_alg_file(kind), "w") as f:
+        json.dump(alg, f)
+    print(f"pmc probe {kind} done", flush=True)
+
+
+def _kernel_class(name: str):
+    """Class of a dispatched kernel for the counter summaries, from its
+    demangled name: the calibration copy, or '<kernel> <fwd|inv> <dtype>'."""
+    if "copyBuffer" in name or "copy_kernel" in name:
+        return "copy"
+    dts = {"StF32": "f32", "StBF16": "bf16", "StF16": "f16"}
+
+    def dtype_of(args):
+        for k, v in dts.items():
+            if k in args:
+                return v
+        return "?"
+    m = re.search(r"plan2d_kernel<([^>]*)>", name)
+    if m:
+        a = [x.strip() for x in m.group(1).split(",")]
+        return f"plan2d {'inv' if a[3] == 'true' else 'fwd'} {dtype_of(m.group(1))}"
+    m = re.search(r"plan1d_kernel<([^>]*)>", name)
+    if m:
+        a = [x.strip() for x in m.group(1).split(",")]
+        return f"plan1d {'inv' if a[1] == 'true' else 'fwd'} {dtype_of(m.group(1))}"
+    m = re.search(r"(finish1d\w*|plan1d_finish_kernel)<([^>]*)>", name)
+    if m:
+        return f"finish1d {dtype_of(m.group(2))}"
+    for k in ("fwd2d", "inv2d"):
+        m = re.search(k + r"\w*kernel<([^>]*)>", name)
+        if m:
+            return f"{k} {dtype_of(m.group(1))}"
+    return None
+
+
+def write_traffic_kind(kind: str, fetch_csv: str, write_csv: str, command: str, out_md: str):
+    """Summarise the two counter passes of pmc_probe_kind into HBM bytes per
+    dispatch of each kernel class, scaled by what the same counter reads for
+    the 64 MiB reference copy, against the algorithmic bytes."""
+    import csv
+    import statistics
+    with open(_alg_file(kind)) as f:
+        alg = json.load(f)
+
+    def per_class(path, counter):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            c = _kernel_class(r["Kernel_Name"])
+            if c is not None:
+                out.setdefault(c, []).append(float(r["Counter_Value"]))
+        return {k: (statistics.median(v), len(v)) for k, v in out.items()}
+
+    fetch = per_class(fetch_csv, "FETCH_SIZE")
+    write = per_class(write_csv, "WRITE_SIZE")
+    ref_kib = H * W * 4 / 1024.0
+    f_scale, w_scale = ref_kib / fetch["copy"][0], ref_kib / write["copy"][0]
+    with open(out_md, "w") as f:
+        f.write(f"# HBM traffic per dispatch: {PMC_KINDS[kind]}\n\nCommand: `{command}`\n\n")
+        f.write(f"Reference: a 64 MiB device copy reads FETCH_SIZE = {fetch['copy'][0]:.0f} KiB "
+                f"(scale {f_scale:.4f}) and WRITE_SIZE = {write['copy'][0]:.0f} KiB (scale {w_scale:.4f}); "
+                "each kernel's counters are scaled by the same factor.  Medians over the dispatches.\n\n")
+        f.write("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read MiB | HBM write MiB "
+                "| algorithmic MiB | total / algorithmic |\n|---|---|---|---|---|---|---|---|\n")
+        for k in sorted(set(fetch) | set(write)):
+            if k == "copy":
+                continue
+            fr, n = fetch.get(k, (0.0, 0))
+            wr, _ = write.get(k, (0.0, 0))
+            rd, wb = fr * f_scale * 1024.0, wr * w_scale * 1024.0
+            a = alg.get(k)
+            ratio = f"{(rd + wb) / a:.4f}" if a else "n/a (small)"
+            am = f"{a / 2**20:.2f}" if a is not None else "?"
+            f.write(f"| {k} | {n} | {fr:.0f} | {wr:.0f} | {rd / 2**20:.2f} | {wb / 2**20:.2f} | {am} | {ratio} |\n")
+    print(open(out_md).read())
+
+
 def write_kernel_stats(stats_csv: str, command: str, out_md: str, max_rows: int = 30):
     """Summarise a rocprofv3 --kernel-trace --stats CSV (one row per kernel
     name) into a short Markdown table under profiles/."""
@@ -546,6 +702,10 @@ def main():
                     help="run the dispatches profiled by the rocprofv3 counter passes and exit")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="summarise two rocprofv3 counter CSVs into the profiles/ traffic file")
+    ap.add_argument("--pmc-probe-kind", choices=sorted(PMC_KINDS),
+                    help="run the dispatches of one of the other counter probes and exit")
+    ap.add_argument("--write-traffic-kind", nargs=5, metavar=("KIND", "FETCH_CSV", "WRITE_CSV", "COMMAND", "OUT_MD"),
+                    help="summarise the counter passes of --pmc-probe-kind into a profiles/ Markdown table")
     ap.add_argument("--write-kernel-stats", nargs=3, metavar=("STATS_CSV", "COMMAND", "OUT_MD"),
                     help="summarise a rocprofv3 kernel stats CSV into a Markdown table")
     ap.add_argument("--suite", action="store_true",
@@ -563,6 +723,12 @@ def main():
         return
     if args.volumes:
         volumes()
+        return
+    if args.pmc_probe_kind:
+        pmc_probe_kind(args.pmc_probe_kind)
+        return
+    if args.write_traffic_kind:
+        write_traffic_kind(*args.write_traffic_kind)
         return
     if args.write_kernel_stats:
         write_kernel_stats(*args.write_kernel_stats)

@@ -24,7 +24,15 @@ def dtype_code(t: torch.Tensor) -> int:
         raise TypeError(f"unsupported dtype {t.dtype}; use float32, bfloat16 or float16") from None
 
 
+# The raw handle of the current stream without building a torch.cuda.Stream
+# object per call (a few microseconds each, which the autograd step pays
+# twice); torch.cuda.current_stream is the fallback.
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream(dev) -> int:
+    if _raw_stream is not None and dev.index is not None:
+        return _raw_stream(dev.index)
     return torch.cuda.current_stream(dev).cuda_stream
 
 
