@@ -51,13 +51,19 @@ int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels, 
     auto it = g_table.find(key_2d(dtype, inverse, h, w, levels));
     if (it != g_table.end()) return it->second;
     if (fallback >= 0) return fallback;
-    // measured defaults (4096^2, 5 levels, cold HBM): FP32, 32 x 256 tiles
-    // (4 x 4 registers per thread, 512 threads), one tile per work-group,
-    // blocks dealt round-robin to the XCDs, the analysis with two-row
-    // wavefronts (26.6-27.0 us against 27.1-27.7 us, level 3 by shuffles);
-    // 16-bit analysis, the 256-thread 32 x 256 tiles (16.1-16.4 us against
-    // 18.0 us for 32 x 512)
-    if (dtype == 0) return inverse ? 1 : 14;
+    // measured defaults (4096^2, 5 levels, cold HBM, one tile per
+    // work-group, blocks dealt round-robin to the XCDs):
+    //  - FP32 analysis: 32 x 256 tiles, 4 x 4 registers per thread, 512
+    //    threads, two-row wavefronts (26.0-26.2 us; level 3 by shuffles);
+    //  - FP32 synthesis of large images: 64 x 256 tiles, 8 x 4 registers per
+    //    thread, 512 threads (23.5 us against 24.4 us for 32 x 256 with
+    //    4 x 4); smaller images keep the 32-row tiles;
+    //  - 16-bit data of rows of 1024 or more: 32 x 512 tiles, 8 x 8
+    //    registers per thread, 256 threads, level 3 in registers (analysis
+    //    15.1 us against 15.9 us, synthesis 14.0 against 14.3 us); narrower
+    //    images keep the 32 x 256 analysis and 32 x 512 synthesis tiles.
+    if (dtype == 0) return inverse ? (h * w >= ((int64_t)1 << 22) ? 17 : 1) : 14;
+    if (w >= 1024) return 15;
     return inverse ? 1 : 0;
 }
 
