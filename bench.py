@@ -752,6 +752,7 @@ def main():
     import numpy as np
     import torch
 
+    from paper_1002_2184_amd import _abi
     from paper_1002_2184_amd import autograd as AG
     from paper_1002_2184_amd import transform as T
     from workloads import generators as G
@@ -776,11 +777,15 @@ def main():
     # multiple of NSTREAMS), so no buffer is shared between streams.
     streams = [stream] + [torch.cuda.Stream(dev) for _ in range(NSTREAMS - 1)]
 
+    # the steps call the C ABI through its binding with the stream handle
+    # (pointers taken once), which keeps the host ahead of the device
+    sh = [q.cuda_stream for q in streams]
+    xp, yp, zp = ([t.data_ptr() for t in ts] for ts in (xs, ys, zs))
+
     def step(k, nstreams=NSTREAMS):
-        s = k % SETS
-        with torch.cuda.stream(streams[k % nstreams]):
-            T.fwd2d(xs[s], LEVELS, out=ys[s])
-            T.inv2d(ys[s], LEVELS, out=zs[s])
+        s, q = k % SETS, sh[k % nstreams]
+        _abi.check(_abi.haar_fwd_2d(xp[s], yp[s], H, W, LEVELS, 1, 0, q))
+        _abi.check(_abi.haar_inv_2d(yp[s], zp[s], H, W, LEVELS, 1, 0, q))
 
     def timed_steps(nstreams):
         """ms per step of K steps on nstreams streams, bracketed by events on
@@ -811,22 +816,29 @@ def main():
         step(k, 1)
     ms_step_one = timed_steps(1)
 
-    # average duration of each kernel: K back-to-back launches of it alone,
-    # bracketed by HIP events on the launch stream (the sets still rotate,
-    # so every launch reads data last touched 15 launches earlier)
+    # average duration of each kernel: back-to-back launches of it alone,
+    # bracketed by HIP events on the launch stream (the sets still rotate, so
+    # every launch reads data last touched 15 launches earlier).  The start
+    # event is queued behind 16 untimed launches, so that the timed ones are
+    # already queued when it fires: the figure is the kernel's duration, not
+    # the latency of a first launch on an idle device.  At least 200 launches.
     def per_launch_ms(fn):
+        reps = max(args.steps, 200)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        for k in range(16):
+            fn(k % SETS)
         e0.record(stream)
-        for k in range(args.steps):
+        for k in range(reps):
             fn(k % SETS)
         e1.record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.steps
+        return e0.elapsed_time(e1) / reps
 
-    fwd_avg = per_launch_ms(lambda s: T.fwd2d(xs[s], LEVELS, out=ys[s]))
-    inv_avg = per_launch_ms(lambda s: T.inv2d(ys[s], LEVELS, out=zs[s]))
+    q0 = stream.cuda_stream
+    fwd_avg = per_launch_ms(lambda s: _abi.check(_abi.haar_fwd_2d(xp[s], yp[s], H, W, LEVELS, 1, 0, q0)))
+    inv_avg = per_launch_ms(lambda s: _abi.check(_abi.haar_inv_2d(yp[s], zp[s], H, W, LEVELS, 1, 0, q0)))
 
     # correctness spot check of the timed outputs (GPU side)
     rt_err = float((zs[0] - xs[0]).abs().max() / xs[0].pow(2).mean().sqrt())

@@ -28,10 +28,21 @@ namespace haar {
 // ---------------------------------------------------------------------------
 // 2x2 butterflies
 // ---------------------------------------------------------------------------
+// EX (exact): the approximation path carries a compensated pair (hi + lo),
+// rounded once when stored; used whenever the detail bands or the deepest LL
+// are stored in FP32.  With 16-bit outputs (EX = false) plain FP32 sums are
+// far more accurate than the output format (2^-24 against 2^-9 relative per
+// rounding), so the pair is not formed (lo stays zero) and the analysis does
+// about a quarter of the vector work less.
+
 // Analysis of a full 2x2 block of exact floats (x00 x01 / x10 x11).
+template <bool EX = true>
 __device__ __forceinline__ void ana_full_f(float x00, float x01, float x10, float x11, df& ll,
                                            float& hl, float& lh, float& hh) {
-    ll = df_scale(df_sum4f(x00, x01, x10, x11), 0.5f);
+    if constexpr (EX)
+        ll = df_scale(df_sum4f(x00, x01, x10, x11), 0.5f);
+    else
+        ll = df{0.5f * ((x00 + x01) + (x10 + x11)), 0.0f};
     const float dr0 = x01 - x00, dr1 = x11 - x10;   // high along width, rows 0/1
     hl = 0.5f * (dr0 + dr1);
     hh = 0.5f * (dr1 - dr0);
@@ -39,32 +50,58 @@ __device__ __forceinline__ void ana_full_f(float x00, float x01, float x10, floa
 }
 
 // Analysis of a full 2x2 block of pairs.
+template <bool EX = true>
 __device__ __forceinline__ void ana_full_df(df x00, df x01, df x10, df x11, df& ll, float& hl,
                                             float& lh, float& hh) {
-    ll = df_scale(df_sum4(x00, x01, x10, x11), 0.5f);
-    const float dr0 = df_diff(x01, x00), dr1 = df_diff(x11, x10);
-    hl = 0.5f * (dr0 + dr1);
-    hh = 0.5f * (dr1 - dr0);
-    lh = 0.5f * (df_diff(x10, x00) + df_diff(x11, x01));
+    if constexpr (EX) {
+        ll = df_scale(df_sum4(x00, x01, x10, x11), 0.5f);
+        const float dr0 = df_diff(x01, x00), dr1 = df_diff(x11, x10);
+        hl = 0.5f * (dr0 + dr1);
+        hh = 0.5f * (dr1 - dr0);
+        lh = 0.5f * (df_diff(x10, x00) + df_diff(x11, x01));
+    } else {
+        ana_full_f<false>(x00.hi, x01.hi, x10.hi, x11.hi, ll, hl, lh, hh);
+    }
 }
 
 // Analysis with the carry rule.  c1: column 2k+1 exists; r1: row 2i+1 exists.
+template <bool EX = true>
 __device__ __forceinline__ void ana_edge_df(df x00, df x01, df x10, df x11, bool r1, bool c1,
                                             df& ll, float& hl, float& lh, float& hh) {
     if (r1 && c1) {
-        ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
+        ana_full_df<EX>(x00, x01, x10, x11, ll, hl, lh, hh);
     } else if (c1) {            // single row: row pass only, column carried
-        ll = df_rs2(df_add(x00, x01));
-        hl = df_round(df_rs2(df_from(df_diff(x01, x00))));
+        if constexpr (EX) {
+            ll = df_rs2(df_add(x00, x01));
+            hl = df_round(df_rs2(df_from(df_diff(x01, x00))));
+        } else {
+            ll = df{(x00.hi + x01.hi) * kRs2Hi, 0.0f};
+            hl = (x01.hi - x00.hi) * kRs2Hi;
+        }
         lh = hh = 0.0f;
     } else if (r1) {            // single column: column pass only, row carried
-        ll = df_rs2(df_add(x00, x10));
-        lh = df_round(df_rs2(df_from(df_diff(x10, x00))));
+        if constexpr (EX) {
+            ll = df_rs2(df_add(x00, x10));
+            lh = df_round(df_rs2(df_from(df_diff(x10, x00))));
+        } else {
+            ll = df{(x00.hi + x10.hi) * kRs2Hi, 0.0f};
+            lh = (x10.hi - x00.hi) * kRs2Hi;
+        }
         hl = hh = 0.0f;
     } else {
         ll = x00;
         hl = lh = hh = 0.0f;
     }
+}
+
+// The approximation rounded to one float (the pair's sum, or hi alone when
+// the pair is not formed).
+template <bool EX>
+__device__ __forceinline__ float acc_round(df a) {
+    if constexpr (EX)
+        return df_round(a);
+    else
+        return a.hi;
 }
 
 // Synthesis of one 2x2 block (inverse of the analysis), with the carry rule.
@@ -154,8 +191,12 @@ __device__ __forceinline__ void thread_rc(int t, int& rg, int& cg) {
     }
 }
 
+template <bool EX = true>
 __device__ __forceinline__ df shfl_xor_df(df a, int m) {
-    return df{__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)};
+    if constexpr (EX)
+        return df{__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)};
+    else
+        return df{__shfl_xor(a.hi, m), 0.0f};
 }
 
 
@@ -206,6 +247,8 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
     const int th = FULL ? TH : (p.h - r0 < TH ? (int)(p.h - r0) : TH);
     const int tw = FULL ? TW : (p.w - c0 < TW ? (int)(p.w - c0) : TW);
     const int lr0 = rg * RY, lc0 = cg * RX;            // local origin of this thread's block
+    // compensated approximation path unless every output of the pass is 16-bit
+    constexpr bool EX = SD::kBytes == 4 || SL::kBytes == 4;
     // the whole register block lies inside the region: every 2x2 block of
     // levels 1 and 2 is complete and its bands are written as vectors
     const bool inb = FULL || (lr0 + RY <= th && lc0 + RX <= tw);
@@ -224,11 +267,11 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
 #pragma unroll
             for (int k = 0; k < B1X; ++k) {
                 if constexpr (FULL) {
-                    ana_full_f(v[2 * i][2 * k], v[2 * i][2 * k + 1], v[2 * i + 1][2 * k],
+                    ana_full_f<EX>(v[2 * i][2 * k], v[2 * i][2 * k + 1], v[2 * i + 1][2 * k],
                                v[2 * i + 1][2 * k + 1], a1[i][k], hl[i][k], lh[i][k], hh[i][k]);
                 } else {
                     const bool r1 = lr0 + 2 * i + 1 < th, c1 = lc0 + 2 * k + 1 < tw;
-                    ana_edge_df(df_from(v[2 * i][2 * k]), df_from(v[2 * i][2 * k + 1]),
+                    ana_edge_df<EX>(df_from(v[2 * i][2 * k]), df_from(v[2 * i][2 * k + 1]),
                                 df_from(v[2 * i + 1][2 * k]), df_from(v[2 * i + 1][2 * k + 1]), r1,
                                 c1, a1[i][k], hl[i][k], lh[i][k], hh[i][k]);
                 }
@@ -262,13 +305,13 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
                 if (inb) {
                     float o[B1X];
 #pragma unroll
-                    for (int k = 0; k < B1X; ++k) o[k] = df_round(a1[i][k]);
+                    for (int k = 0; k < B1X; ++k) o[k] = acc_round<EX>(a1[i][k]);
                     st_vec<SL, B1X>(llp + (R + i) * lp + C, o);
                 } else {
 #pragma unroll
                     for (int k = 0; k < B1X; ++k)
                         if (lr0 + 2 * i < th && lc0 + 2 * k < tw)
-                            st1<SL>(llp + (R + i) * lp + C + k, df_round(a1[i][k]));
+                            st1<SL>(llp + (R + i) * lp + C + k, acc_round<EX>(a1[i][k]));
                 }
             }
             return;
@@ -286,11 +329,11 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
 #pragma unroll
             for (int k = 0; k < B2X; ++k) {
                 if constexpr (FULL) {
-                    ana_full_df(a1[2 * i][2 * k], a1[2 * i][2 * k + 1], a1[2 * i + 1][2 * k],
+                    ana_full_df<EX>(a1[2 * i][2 * k], a1[2 * i][2 * k + 1], a1[2 * i + 1][2 * k],
                                 a1[2 * i + 1][2 * k + 1], a2[i][k], hl[i][k], lh[i][k], hh[i][k]);
                 } else {
                     const bool r1 = l1r + 2 * i + 1 < th1, c1 = l1c + 2 * k + 1 < tw1;
-                    ana_edge_df(a1[2 * i][2 * k], a1[2 * i][2 * k + 1], a1[2 * i + 1][2 * k],
+                    ana_edge_df<EX>(a1[2 * i][2 * k], a1[2 * i][2 * k + 1], a1[2 * i + 1][2 * k],
                                 a1[2 * i + 1][2 * k + 1], r1, c1, a2[i][k], hl[i][k], lh[i][k],
                                 hh[i][k]);
                 }
@@ -324,13 +367,13 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
                 if (inb) {
                     float o[B2X];
 #pragma unroll
-                    for (int k = 0; k < B2X; ++k) o[k] = df_round(a2[i][k]);
+                    for (int k = 0; k < B2X; ++k) o[k] = acc_round<EX>(a2[i][k]);
                     st_vec<SL, B2X>(llp + (R + i) * lp + C, o);
                 } else {
 #pragma unroll
                     for (int k = 0; k < B2X; ++k)
                         if (l1r + 2 * i < th1 && l1c + 2 * k < tw1)
-                            st1<SL>(llp + (R + i) * lp + C + k, df_round(a2[i][k]));
+                            st1<SL>(llp + (R + i) * lp + C + k, acc_round<EX>(a2[i][k]));
                 }
             }
             return;
@@ -349,14 +392,14 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
         df x00, x01, x10, x11;
         if constexpr (B2X == 1) {
             x00 = a2[0][0];
-            x01 = shfl_xor_df(a2[0][0], 1);
-            x10 = shfl_xor_df(a2[0][0], 8);
-            x11 = shfl_xor_df(a2[0][0], 9);
+            x01 = shfl_xor_df<EX>(a2[0][0], 1);
+            x10 = shfl_xor_df<EX>(a2[0][0], 8);
+            x11 = shfl_xor_df<EX>(a2[0][0], 9);
         } else {
             x00 = a2[0][0];
             x01 = a2[0][1];
-            x10 = shfl_xor_df(a2[0][0], 8);
-            x11 = shfl_xor_df(a2[0][1], 8);
+            x10 = shfl_xor_df<EX>(a2[0][0], 8);
+            x11 = shfl_xor_df<EX>(a2[0][1], 8);
         }
         int i = rgl >> 1, k = B2X == 1 ? (cgl >> 1) : cgl;   // level-3 position in the patch
         bool active = (rgl & 1) == 0 && (B2X == 2 || (cgl & 1) == 0);
@@ -368,21 +411,21 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
             if (lev > 3) {
                 const int cs = CS3 << (lev - 4), rs = 16 << (lev - 4);
                 x00 = ll;
-                x01 = shfl_xor_df(ll, cs);
-                x10 = shfl_xor_df(ll, rs);
-                x11 = shfl_xor_df(ll, cs | rs);
+                x01 = shfl_xor_df<EX>(ll, cs);
+                x10 = shfl_xor_df<EX>(ll, rs);
+                x11 = shfl_xor_df<EX>(ll, cs | rs);
                 active = active && (i & 1) == 0 && (k & 1) == 0;
                 i >>= 1;
                 k >>= 1;
             }
-            ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
+            ana_full_df<EX>(x00, x01, x10, x11, ll, hl, lh, hh);
             if (active) {
                 const int64_t hs = ceil_shift(p.h, lev), ws = ceil_shift(p.w, lev);
                 const int64_t R = (r0 >> lev) + i, C = (wc0 >> lev) + k;
                 st1<SD>(det + R * dp + ws + C, hl);
                 st1<SD>(det + (hs + R) * dp + C, lh);
                 st1<SD>(det + (hs + R) * dp + ws + C, hh);
-                if (lev == L) st1<SL>(llp + R * lp + C, df_round(ll));
+                if (lev == L) st1<SL>(llp + R * lp + C, acc_round<EX>(ll));
             }
             if (lev == L) return;
         }
@@ -408,8 +451,8 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
         if constexpr (B2X == 1) {
             x00 = a2[0][0];
             x10 = a2[1][0];
-            x01 = shfl_xor_df(a2[0][0], 1);
-            x11 = shfl_xor_df(a2[1][0], 1);
+            x01 = shfl_xor_df<EX>(a2[0][0], 1);
+            x11 = shfl_xor_df<EX>(a2[1][0], 1);
             active = (lane & 1) == 0;
             k3 = cg >> 1;
         } else {
@@ -424,17 +467,17 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
         if (active) {
             df ll;
             float hl, lh, hh;
-            ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
+            ana_full_df<EX>(x00, x01, x10, x11, ll, hl, lh, hh);
             const int64_t hs = ceil_shift(p.h, 3), ws = ceil_shift(p.w, 3);
             const int64_t R = (r0 >> 3) + rg, C = (c0 >> 3) + k3;
             st1<SD>(det + R * dp + ws + C, hl);
             st1<SD>(det + (hs + R) * dp + C, lh);
             st1<SD>(det + (hs + R) * dp + ws + C, hh);
             if (L == 3) {
-                st1<SL>(llp + R * lp + C, df_round(ll));
+                st1<SL>(llp + R * lp + C, acc_round<EX>(ll));
             } else {
                 Bhi[rg * (TW / 8) + k3] = ll.hi;
-                Blo[rg * (TW / 8) + k3] = ll.lo;
+                if constexpr (EX) Blo[rg * (TW / 8) + k3] = ll.lo;
             }
         }
         if (L == 3) return;
@@ -452,21 +495,21 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
         if constexpr (B2X == 1) {
             const df a = a2[0][0];
             x00 = a;
-            x01 = df{__shfl_xor(a.hi, 1), __shfl_xor(a.lo, 1)};
-            x10 = df{__shfl_xor(a.hi, 32), __shfl_xor(a.lo, 32)};
-            x11 = df{__shfl_xor(a.hi, 33), __shfl_xor(a.lo, 33)};
+            x01 = shfl_xor_df<EX>(a, 1);
+            x10 = shfl_xor_df<EX>(a, 32);
+            x11 = shfl_xor_df<EX>(a, 33);
         } else {
             x00 = a2[0][0];
             x01 = a2[0][1];
-            x10 = df{__shfl_xor(a2[0][0].hi, 32), __shfl_xor(a2[0][0].lo, 32)};
-            x11 = df{__shfl_xor(a2[0][1].hi, 32), __shfl_xor(a2[0][1].lo, 32)};
+            x10 = shfl_xor_df<EX>(a2[0][0], 32);
+            x11 = shfl_xor_df<EX>(a2[0][1], 32);
         }
         const bool active = B2X == 1 ? (lane & 33) == 0 : lane < 32;
         if (active) {
             const int k = B2X == 1 ? (lane >> 1) : lane;     // level-3 column in the tile
             df ll;
             float hl, lh, hh;
-            ana_full_df(x00, x01, x10, x11, ll, hl, lh, hh);
+            ana_full_df<EX>(x00, x01, x10, x11, ll, hl, lh, hh);
             const int64_t hs = ceil_shift(p.h, 3), ws = ceil_shift(p.w, 3);
             const int64_t R = (r0 >> 3) + w, C = (c0 >> 3) + cb3 + k;
             if constexpr (MAP == 2) {
@@ -481,10 +524,10 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
                 st1<SD>(det + (hs + R) * dp + ws + C, hh);
             }
             if (L == 3) {
-                st1<SL>(llp + R * lp + C, df_round(ll));
+                st1<SL>(llp + R * lp + C, acc_round<EX>(ll));
             } else {
                 Bhi[w * (TW / 8) + cb3 + k] = ll.hi;
-                Blo[w * (TW / 8) + cb3 + k] = ll.lo;
+                if constexpr (EX) Blo[w * (TW / 8) + cb3 + k] = ll.lo;
             }
         }
         if (L == 3) return;
@@ -498,7 +541,7 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
             for (int k = 0; k < B2X; ++k) {
                 const int idx = ((lr0 >> 2) + i) * (TW / 4) + (lc0 >> 2) + k;
                 Ahi[idx] = a2[i][k].hi;
-                Alo[idx] = a2[i][k].lo;
+                if constexpr (EX) Alo[idx] = a2[i][k].lo;
             }
     }
     __syncthreads();
@@ -521,22 +564,23 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
             const int i = b / bw, k = b - i * bw;
             const bool r1 = 2 * i + 1 < rh, c1 = 2 * k + 1 < rw;
             const int i0 = (2 * i) * pin + 2 * k;
-            const df x00 = {ihi[i0], ilo[i0]};
-            const df x01 = c1 ? df{ihi[i0 + 1], ilo[i0 + 1]} : df{0.0f, 0.0f};
-            const df x10 = r1 ? df{ihi[i0 + pin], ilo[i0 + pin]} : df{0.0f, 0.0f};
-            const df x11 = (r1 && c1) ? df{ihi[i0 + pin + 1], ilo[i0 + pin + 1]} : df{0.0f, 0.0f};
+            auto lo_at = [&](int q) { return EX ? ilo[q] : 0.0f; };
+            const df x00 = {ihi[i0], lo_at(i0)};
+            const df x01 = c1 ? df{ihi[i0 + 1], lo_at(i0 + 1)} : df{0.0f, 0.0f};
+            const df x10 = r1 ? df{ihi[i0 + pin], lo_at(i0 + pin)} : df{0.0f, 0.0f};
+            const df x11 = (r1 && c1) ? df{ihi[i0 + pin + 1], lo_at(i0 + pin + 1)} : df{0.0f, 0.0f};
             df ll;
             float hl, lh, hh;
-            ana_edge_df(x00, x01, x10, x11, r1, c1, ll, hl, lh, hh);
+            ana_edge_df<EX>(x00, x01, x10, x11, r1, c1, ll, hl, lh, hh);
             const int64_t R = R0 + i, C = C0 + k;
             if (c1) st1_cached<SD>(det + R * dp + ws + C, hl);
             if (r1) st1_cached<SD>(det + (hs + R) * dp + C, lh);
             if (r1 && c1) st1_cached<SD>(det + (hs + R) * dp + ws + C, hh);
             if (lev == L) {
-                st1_cached<SL>(llp + R * lp + C, df_round(ll));
+                st1_cached<SL>(llp + R * lp + C, acc_round<EX>(ll));
             } else {
                 ohi[i * pout + k] = ll.hi;
-                olo[i * pout + k] = ll.lo;
+                if constexpr (EX) olo[i * pout + k] = ll.lo;
             }
         }
         rh = bh;
