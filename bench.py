@@ -280,14 +280,19 @@ def write_traffic_kind(kind: str, fetch_csv: str, write_csv: str, command: str, 
         alg = json.load(f)
 
     def per_class(path, counter):
-        out = {}
+        out, copies = {}, []
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
             c = _kernel_class(r["Kernel_Name"])
-            if c is not None:
+            if c == "copy":      # the reference copies are the probe's first 4 dispatches
+                copies.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+            elif c is not None:
                 out.setdefault(c, []).append(float(r["Counter_Value"]))
-        return {k: (statistics.median(v), len(v)) for k, v in out.items()}
+        res = {k: (statistics.median(v), len(v)) for k, v in out.items()}
+        ref = [v for _, v in sorted(copies)[:4]]
+        res["copy"] = (statistics.median(ref), len(ref))
+        return res
 
     fetch = per_class(fetch_csv, "FETCH_SIZE")
     write = per_class(write_csv, "WRITE_SIZE")
@@ -313,25 +318,55 @@ def write_traffic_kind(kind: str, fetch_csv: str, write_csv: str, command: str, 
     print(open(out_md).read())
 
 
+def _isolated_averages(trace_csv: str):
+    """Per kernel name: (dispatches that overlapped no other dispatch, their
+    average duration in us), from a rocprofv3 kernel-trace CSV.  Kernels that
+    ran concurrently on other streams share the device, so only isolated
+    dispatches give the kernel's own duration."""
+    import csv
+    rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+            for r in csv.DictReader(open(trace_csv))]
+    rows.sort()
+    out = {}
+    end_max = -1
+    for i, (a, b, name) in enumerate(rows):
+        nxt = rows[i + 1][0] if i + 1 < len(rows) else None
+        alone = a >= end_max and (nxt is None or nxt >= b)
+        end_max = max(end_max, b)
+        if alone:
+            n, t = out.get(name, (0, 0.0))
+            out[name] = (n + 1, t + (b - a) / 1e3)
+    return {k: (n, t / n) for k, (n, t) in out.items()}
+
+
 def write_kernel_stats(stats_csv: str, command: str, out_md: str, max_rows: int = 30):
     """Summarise a rocprofv3 --kernel-trace --stats CSV (one row per kernel
-    name) into a short Markdown table under profiles/."""
+    name) into a short Markdown table under profiles/; with the kernel-trace
+    CSV beside it, also the average over the dispatches that ran alone."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     total = len(rows)
     rows = rows[:max_rows]
+    trace = stats_csv.replace("_kernel_stats.csv", "_kernel_trace.csv")
+    iso = _isolated_averages(trace) if os.path.exists(trace) else {}
     with open(out_md, "w") as f:
         f.write(f"# Kernel durations (rocprofv3 --kernel-trace --stats)\n\nCommand: `{command}`\n\n")
         if total > len(rows):
             f.write(f"The {len(rows)} kernels with the most GPU time, of {total}.\n\n")
-        f.write("| kernel | calls | average us | min us | max us | share of GPU time |\n|---|---|---|---|---|---|\n")
+        if iso:
+            f.write("`alone`: dispatches that overlapped no other dispatch (the benchmark also runs "
+                    "steps on two streams at once, whose kernels share the device), and their average.\n\n")
+        f.write("| kernel | calls | average us | min us | max us | share of GPU time | alone | average alone us |\n"
+                "|---|---|---|---|---|---|---|---|\n")
         for r in rows:
             name = r["Name"]
             short = name if len(name) <= 110 else name[:107] + "..."
+            n_iso, t_iso = iso.get(name, (0, 0.0))
             f.write(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
-                    f"{float(r['Percentage']):.1f} % |\n")
+                    f"{float(r['Percentage']):.1f} % | {n_iso} | "
+                    f"{(f'{t_iso:.2f}' if n_iso else '-')} |\n")
     print(open(out_md).read())
 
 
