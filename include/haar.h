@@ -264,11 +264,12 @@ int haar_max_levels_3d(int64_t depth, int64_t height, int64_t width);
  * haar_plan_set_config: a persistent grid (the resident work-groups of the
  * device) walking the list with a stride, a persistent grid claiming units
  * from an atomic counter, or one work-group per unit, the last for 2D also
- * with the units of each XCD contiguous and write-back stores.  Defaults, as
- * measured: 2D analysis plans run one tile per work-group, XCD-contiguous,
- * with write-back stores (rows of most images start inside a cache line,
- * and neighbouring tiles then share lines); 2D synthesis plans and all 1D
- * plans run one unit per work-group.  A 1D analysis plan with items deeper
+ * with the units of each XCD contiguous (so that neighbouring tiles share
+ * one L2), with or without write-back stores.  Defaults, as measured: 2D
+ * analysis plans run one tile per work-group, XCD-contiguous, with
+ * write-back stores (rows of most images start inside a cache line, and
+ * neighbouring tiles then share lines); 2D synthesis plans and 1D plans run
+ * one unit per work-group.  A 1D analysis plan with items deeper
  * than 12 levels enqueues a second, small kernel that finishes those items,
  * one work-group per item.  The plan itself holds host memory only; the
  * device-side tables and counters live in a caller-owned workspace of
@@ -321,10 +322,11 @@ int haar_plan_info(const haar_plan* plan, int64_t* tiles, int32_t* grid);
  * b, b + G, b + 2G, ... of the list; 1: a persistent grid whose work-groups
  * claim units from an atomic counter; 2: one work-group per unit; 3 (2D
  * only): one work-group per unit, the units of each XCD contiguous in the
- * list, outputs written with write-back instead of streaming stores.
- * 2D: config = tile shape + 2 * schedule, tile shape 0: 32 rows x 16
- * vectors, 1: 32 rows x 32 vectors (configs 0..7).  1D: config = schedule
- * (0..2). */
+ * list, outputs written with write-back instead of streaming stores; 4 (2D
+ * only): one work-group per unit, the units of each XCD contiguous, streaming
+ * stores.  2D: config = tile shape + 2 * schedule, tile shape 0: 32 rows x
+ * 16 vectors, 1: 32 rows x 32 vectors (configs 0..9).  1D: config =
+ * schedule (0..2). */
 int haar_plan_set_config(haar_plan* plan, int32_t config);
 /* Autotune a plan: time executes of every configuration on `stream`
  * (hipEvents; synchronises the stream; overwrites the items' outputs), keep

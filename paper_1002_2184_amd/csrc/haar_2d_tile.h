@@ -547,9 +547,54 @@ __device__ __forceinline__ void fwd2d_body(const Pass2D& p, int64_t item, int64_
     __syncthreads();
 
     // The remaining levels are small (at most (TH/8) x (TW/8) blocks): the
-    // first wavefront does them alone, ordered by wavefront-level barriers, so
-    // the other wavefronts of the work-group can retire.
+    // first wavefront does them alone, so the other wavefronts of the
+    // work-group can retire.
     if (t >= 64) return;
+    constexpr int BH4 = TH / 16, BW4 = TW / 16;      // level-4 blocks of a full tile
+    if constexpr (FULL && BH4 * BW4 <= 64 && (BW4 & (BW4 - 1)) == 0) {
+        if (first == 4) {
+            // Full tile with LL3 (TH/8 x TW/8, pitch TW/8) in LDS: lane
+            // i * BW4 + k takes level-4 block (i, k) straight from LDS; level
+            // 5 pairs lanes by xor shuffles (column partner lane ^ 1, row
+            // partner lane ^ BW4), with no second LDS round trip.  Lanes past
+            // the blocks read a valid block again and store nothing.
+            constexpr int P3 = TW / 8;
+            const int lane = t;
+            const int bl = lane < BH4 * BW4 ? lane : lane % (BH4 * BW4);
+            const int i = bl / BW4, k = bl % BW4;
+            const int i0 = (2 * i) * P3 + 2 * k;
+            auto at = [&](int q) { return df{Bhi[q], EX ? Blo[q] : 0.0f}; };
+            df ll;
+            float hl, lh, hh;
+            ana_full_df<EX>(at(i0), at(i0 + 1), at(i0 + P3), at(i0 + P3 + 1), ll, hl, lh, hh);
+            const bool own = lane < BH4 * BW4;
+            {
+                const int64_t hs = ceil_shift(p.h, 4), ws = ceil_shift(p.w, 4);
+                const int64_t R = (r0 >> 4) + i, C = (c0 >> 4) + k;
+                if (own) {
+                    st1_cached<SD>(det + R * dp + ws + C, hl);
+                    st1_cached<SD>(det + (hs + R) * dp + C, lh);
+                    st1_cached<SD>(det + (hs + R) * dp + ws + C, hh);
+                    if (L == 4) st1_cached<SL>(llp + R * lp + C, acc_round<EX>(ll));
+                }
+            }
+            if (L == 4) return;
+            static_assert(BH4 % 2 == 0 && BW4 % 2 == 0, "level-5 blocks of a full tile");
+            const df x01 = shfl_xor_df<EX>(ll, 1), x10 = shfl_xor_df<EX>(ll, BW4),
+                     x11 = shfl_xor_df<EX>(ll, BW4 + 1);
+            df l5;
+            ana_full_df<EX>(ll, x01, x10, x11, l5, hl, lh, hh);
+            if (own && (i & 1) == 0 && (k & 1) == 0) {
+                const int64_t hs = ceil_shift(p.h, 5), ws = ceil_shift(p.w, 5);
+                const int64_t R = (r0 >> 5) + (i >> 1), C = (c0 >> 5) + (k >> 1);
+                st1_cached<SD>(det + R * dp + ws + C, hl);
+                st1_cached<SD>(det + (hs + R) * dp + C, lh);
+                st1_cached<SD>(det + (hs + R) * dp + ws + C, hh);
+                st1_cached<SL>(llp + R * lp + C, acc_round<EX>(l5));
+            }
+            return;
+        }
+    }
     for (int lev = first; lev <= L; ++lev) {
         const bool odd = lev & 1;
         const float* ihi = odd ? Ahi : Bhi;

@@ -277,7 +277,7 @@ static int own_lines_1d(const Pass1D& p, bool inverse, int ebx, int ebd, int64_t
 int run_1d(const void* in, void* out, int64_t N, int L, int64_t batch, int dtype, bool inverse,
            hipStream_t s, int cfg_override) {
     const int eb = elem_bytes(dtype);
-    const int cfg = cfg_override >= 0 ? cfg_override : choose_config_1d(dtype, inverse, N, L);
+    const int cfg = cfg_override >= 0 ? cfg_override : choose_config_1d(dtype, inverse, N, L, batch);
     const Chunk1D cc = chunk_config_1d(cfg);
     const int depth = log2_int(cc.chunk());
 

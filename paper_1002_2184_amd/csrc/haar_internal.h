@@ -26,7 +26,7 @@ int fault_injected();
 // fallback >= 0: returned when neither a forced choice nor a tuning-table
 // entry exists (plans pass their own default shape).
 int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels, int fallback = -1);
-int choose_config_1d(int dtype, bool inverse, int64_t n, int levels);
+int choose_config_1d(int dtype, bool inverse, int64_t n, int levels, int64_t batch = 1);
 
 int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch, int dtype,
            bool inverse, hipStream_t s, int cfg_override);

@@ -113,12 +113,15 @@ __device__ __forceinline__ void walk_units(unsigned n, unsigned* ctr, unsigned* 
     }
 }
 
-// WB: XCD-contiguous units and write-back stores (WriteBack<S>), so that the
-// partial cache lines that neighbouring tiles of a misaligned image share are
-// merged in L2 instead of being streamed to HBM twice.
+// REMAP: XCD-contiguous units (one work-group per unit): neighbouring tiles of
+// an image run on one XCD, so the partial cache lines they share (rows of
+// most images start inside a line) are fetched into that XCD's L2 once.
+// WB: outputs with write-back stores (WriteBack<S>), so that partial lines
+// written by two neighbouring tiles merge in L2 instead of being streamed to
+// HBM twice.
 // At least 5 wavefronts per SIMD: the 16-bit analysis kernels sit at the
 // 96-register boundary of that occupancy.
-template <class S, int GY, int GX, bool INV, bool DYN, bool WB>
+template <class S, int GY, int GX, bool INV, bool DYN, bool REMAP, bool WB>
 __global__ __launch_bounds__(GY* GX) __attribute__((amdgpu_waves_per_eu(5))) void plan2d_kernel(const PlanItem2D* __restrict__ items,
                                                         const PlanTile2D* __restrict__ tiles,
                                                         unsigned ntiles, unsigned* ctr) {
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(GY* GX) __attribute__((amdgpu_waves_per_eu(5))) voi
     using G = Geo2D<S, 4, RX, GY, GX>;
     __shared__ float sm[G::SMEM];                          // analysis levels 3..L
     __shared__ unsigned s_slot;
-    walk_units<DYN, WB, false>(ntiles, ctr, &s_slot, [&](unsigned unit) {
+    walk_units<DYN, REMAP, false>(ntiles, ctr, &s_slot, [&](unsigned unit) {
         const PlanTile2D d = tiles[unit];
         const PlanItem2D it = items[d.item];
         Pass2D p{};
@@ -257,7 +260,8 @@ struct haar_plan {
     int inverse = 0;
     int cfg = 1;                       // 2D tile configuration (0: 32 rows x 16 vectors, 1: x 32)
     int sched = 0;                     // 0: strided work-list walk, 1: atomic claiming, 2: one unit per
-                                       // work-group, 3 (2D): 2 with XCD-contiguous units, write-back stores
+                                       // work-group, 3 (2D): 2 with XCD-contiguous units, write-back stores,
+                                       // 4 (2D): 2 with XCD-contiguous units
     std::vector<PlanItem2D> items2;
     std::vector<PlanTile2D> tiles2[2];  // per tile configuration
     std::vector<PlanItem1D> items1;
@@ -275,7 +279,8 @@ namespace {
 
 constexpr int kPlanCfgs2D = 2;          // tile configurations with plan kernels: 0 and 1
 constexpr int kPlanScheds1D = 3;        // 0 strided walk, 1 atomic claiming, 2 one unit per work-group
-constexpr int kPlanScheds2D = 4;        // the same, and 3: 2 with XCD-contiguous units and write-back stores
+constexpr int kPlanScheds2D = 5;        // the same, 3: 2 with XCD-contiguous units and write-back stores,
+                                        // 4: 2 with XCD-contiguous units
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -318,21 +323,25 @@ hipError_t launch_plan2d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
         hipLaunchKernelGGL(kernel, dim3(g), dim3(threads), 0, s, items, tiles, n, ctr);
         return hipGetLastError();
     };
-    const bool inv = pl->inverse != 0, dyn = pl->sched == 1, wb = pl->sched == 3;
-    if (pl->cfg == 0) {
-        if (dyn) return inv ? go(plan2d_kernel<S, 8, 32, true, true, false>, 256)
-                            : go(plan2d_kernel<S, 8, 32, false, true, false>, 256);
-        if (wb) return inv ? go(plan2d_kernel<S, 8, 32, true, false, true>, 256)
-                           : go(plan2d_kernel<S, 8, 32, false, false, true>, 256);
-        return inv ? go(plan2d_kernel<S, 8, 32, true, false, false>, 256)
-                   : go(plan2d_kernel<S, 8, 32, false, false, false>, 256);
+    const bool inv = pl->inverse != 0;
+    // schedules: 0 strided walk, 1 claiming, 2 one unit per work-group,
+    // 3 the same XCD-contiguous with write-back stores, 4 XCD-contiguous
+#define HAAR_PLAN2D_GO(GY_, GX_, DYN_, RM_, WB_)                                               \
+    return inv ? go(plan2d_kernel<S, GY_, GX_, true, DYN_, RM_, WB_>, GY_ * GX_)               \
+               : go(plan2d_kernel<S, GY_, GX_, false, DYN_, RM_, WB_>, GY_ * GX_)
+#define HAAR_PLAN2D_SCHED(GY_, GX_)                                 \
+    switch (pl->sched) {                                            \
+        case 1: HAAR_PLAN2D_GO(GY_, GX_, true, false, false);       \
+        case 3: HAAR_PLAN2D_GO(GY_, GX_, false, true, true);        \
+        case 4: HAAR_PLAN2D_GO(GY_, GX_, false, true, false);       \
+        default: HAAR_PLAN2D_GO(GY_, GX_, false, false, false);     \
     }
-    if (dyn) return inv ? go(plan2d_kernel<S, 8, 64, true, true, false>, 512)
-                        : go(plan2d_kernel<S, 8, 64, false, true, false>, 512);
-    if (wb) return inv ? go(plan2d_kernel<S, 8, 64, true, false, true>, 512)
-                       : go(plan2d_kernel<S, 8, 64, false, false, true>, 512);
-    return inv ? go(plan2d_kernel<S, 8, 64, true, false, false>, 512)
-               : go(plan2d_kernel<S, 8, 64, false, false, false>, 512);
+    if (pl->cfg == 0) {
+        HAAR_PLAN2D_SCHED(8, 32)
+    }
+    HAAR_PLAN2D_SCHED(8, 64)
+#undef HAAR_PLAN2D_SCHED
+#undef HAAR_PLAN2D_GO
 }
 
 template <class S>
@@ -470,8 +479,10 @@ int haar_plan_create_2d(const haar_item_2d* items, int64_t count, int32_t dtype,
     // ms against 0.87 ms claiming tiles with streaming stores, FP32 1.06
     // against 1.33 ms); the synthesis runs one tile per work-group with
     // streaming stores (BF16 0.72 ms against 0.78 ms with the XCD-contiguous
-    // write-back schedule).  Tiles of 32 x 16 vectors for 16-bit data, 32 x
-    // 32 for FP32.
+    // write-back schedule and 0.74 ms XCD-contiguous with streaming stores,
+    // although the latter fetches each shared partial line once: 1.4x the
+    // algorithmic bytes read with the default order).  Tiles of 32 x 16
+    // vectors for 16-bit data, 32 x 32 for FP32.
     const int fb = dtype != 0 ? 0 : 1;
     const int c = choose_config_2d(dtype, inverse != 0, items[order[0]].height, items[order[0]].width,
                                    items[order[0]].levels, fb);

@@ -93,8 +93,8 @@ int main(int argc, char** argv) {
     int64_t tiles = 0;
     int32_t grid = 0;
     expect(haar_plan_info(p, &tiles, &grid), HAAR_OK, "plan2d info");
-    for (int c = 0; c < 8; ++c) expect(haar_plan_set_config(p, c), HAAR_OK, "plan2d config");
-    expect(haar_plan_set_config(p, 8), HAAR_ERR_UNSUPPORTED, "plan2d config range");
+    for (int c = 0; c < 10; ++c) expect(haar_plan_set_config(p, c), HAAR_OK, "plan2d config");
+    expect(haar_plan_set_config(p, 10), HAAR_ERR_UNSUPPORTED, "plan2d config range");
     expect(haar_plan_execute(p, nullptr, 0), HAAR_ERR_WORKSPACE, "plan2d no workspace");
     expect(haar_plan_execute(p, (void*)0x50000000, 0), HAAR_ERR_PLAN, "plan2d not uploaded");
     expect(haar_plan_destroy(p), HAAR_OK, "plan2d destroy");

@@ -227,9 +227,9 @@ def test_plan_validation_and_sizes(abi, monkeypatch):
     # 32x256 f32 tiles: 64x96 -> 2x1, 33x300 -> 2x2
     assert tiles.value == 6
     assert abi.haar_plan_execute(plan, X, 0) == 8          # not uploaded
-    assert abi.haar_plan_set_config(plan, 8) == 9           # configs 0..7 (shape + 2 * schedule)
+    assert abi.haar_plan_set_config(plan, 10) == 9          # configs 0..9 (shape + 2 * schedule)
     assert abi.haar_plan_set_config(plan, -1) == 9
-    assert abi.haar_plan_set_config(plan, 7) == 0
+    assert abi.haar_plan_set_config(plan, 9) == 0
     monkeypatch.setenv("HAAR_FAULT_INJECT", "launch")
     assert abi.haar_plan_upload(plan, X, 0) == 7             # stopped before any HIP call
     assert abi.haar_plan_upload(plan, X + 8, 0) == 6         # misaligned workspace

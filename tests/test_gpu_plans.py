@@ -73,15 +73,16 @@ def test_plan2d_configs_and_tune(P):
     plan = P.Plan2D(xd, yd, lv)
     refs = [oracle.fwd_2d(x.astype(np.float64), L) for x, L in zip(xs, lv)]
     # tile shape + 2 * schedule (strided, atomic claiming, one tile per WG,
-    # one tile per WG XCD-contiguous with write-back stores)
-    for cfg in range(8):
+    # one tile per WG XCD-contiguous with write-back stores, one tile per WG
+    # XCD-contiguous)
+    for cfg in range(10):
         plan.set_config(cfg)
         plan.execute()
         torch.cuda.synchronize()
         for y, r, x in zip(yd, refs, xs):
             check_signal(to_host(y, G.F32).astype(np.float64), r, rms(x), G.F32, f"config {cfg}")
     choice = plan.tune()
-    assert choice in range(8)
+    assert choice in range(10)
     plan.execute()
     torch.cuda.synchronize()
     for y, r, x in zip(yd, refs, xs):
@@ -93,7 +94,7 @@ def test_plan2d_configs_and_tune(P):
 @pytest.mark.parametrize("dt", [G.F32, G.BF16])
 @pytest.mark.parametrize("inverse", [False, True])
 def test_plan2d_every_config_both_directions(P, dt, inverse):
-    """All 8 configurations (2 tile shapes x 4 schedules) of an analysis and of
+    """All 10 configurations (2 tile shapes x 5 schedules) of an analysis and of
     a synthesis plan, two executes each, on images whose rows mostly start
     inside a cache line (odd and even widths, widths not a multiple of 64)."""
     import torch
@@ -110,7 +111,7 @@ def test_plan2d_every_config_both_directions(P, dt, inverse):
     xd = [to_device(x, dt) for x in ins]
     yd = [torch.empty_like(x) for x in xd]
     plan = P.Plan2D(xd, yd, lv, inverse=inverse)
-    for cfg in range(8):
+    for cfg in range(10):
         plan.set_config(cfg)
         for rep in range(2):
             for y in yd:
