@@ -423,16 +423,19 @@ def suite():
         T.fwd1d(x, 16, out=y)
         T.inv1d(y, 16, out=z)
     ms = _timed(one, 200, 20, st)
+    # 16 fwd+inv per graph: one replay of a two-kernel graph would mostly
+    # time the graph launch itself
     g = torch.cuda.CUDAGraph()
     s2 = torch.cuda.Stream()
     s2.wait_stream(st)
     with torch.cuda.stream(s2):
         one()
         with torch.cuda.graph(g, stream=s2):
-            one()
+            for _ in range(16):
+                one()
     st.wait_stream(s2)
     torch.cuda.synchronize()
-    msg = _timed(g.replay, 200, 20, st)
+    msg = _timed(g.replay, 20, 4, st) / 16
     print(json.dumps({"workload": "1d-white-65536-L16 fwd+inv", "us_eager": round(ms * 1e3, 2),
                       "us_graph": round(msg * 1e3, 2),
                       "gbps_eager": round(4 * 65536 * 4 / (ms * 1e-3) / 1e9, 1),
