@@ -230,6 +230,9 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
             if (p.ntl)
                 hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, RY, RX, GY, GX, MAP, true>), dim3(grid),
                                    dim3(GY * GX), 0, s, p, edge, interior);
+            else if (p.wb)
+                hipLaunchKernelGGL((fwd2d_kernel<SX, WriteBack<SD>, WriteBack<SL>, RY, RX, GY, GX, MAP, false>),
+                                   dim3(grid), dim3(GY * GX), 0, s, p, edge, interior);
             else
                 hipLaunchKernelGGL((fwd2d_kernel<SX, SD, SL, RY, RX, GY, GX, MAP, false>), dim3(grid),
                                    dim3(GY * GX), 0, s, p, edge, interior);

@@ -672,6 +672,9 @@ __device__ __forceinline__ void inv2d_load(const Pass2D& p, int64_t item, int64_
     const int lr0 = rg * RY, lc0 = cg * RX;
     const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
     const bool inb = FULL || (lr0 + RY <= th && lc0 + RX <= tw);   // whole block inside
+    // an edge tile's threads whose block lies wholly outside the region have
+    // nothing to read or write (the synthesis has no barrier or shuffle)
+    if (!FULL && (lr0 >= th || lc0 >= tw)) return;
     const typename SD::raw* det = reinterpret_cast<const typename SD::raw*>(p.det) + item * p.det_bstride;
     const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
     const int64_t dp = p.det_pitch, lp = p.ll_pitch;
@@ -771,6 +774,7 @@ __device__ __forceinline__ void inv2d_body(const Pass2D& p, int64_t item, int64_
     const int th1 = (th + 1) >> 1, tw1 = (tw + 1) >> 1;
     const int th2 = (th + 3) >> 2, tw2 = (tw + 3) >> 2;
     const bool inb = FULL || (lr0 + RY <= th && lc0 + RX <= tw);   // whole block inside
+    if (!FULL && (lr0 >= th || lc0 >= tw)) return;                 // nothing of it to write
 
     const typename SL::raw* llp = reinterpret_cast<const typename SL::raw*>(p.ll) + item * p.ll_bstride;
     typename SX::raw* dst =

@@ -54,17 +54,29 @@ int choose_config_2d(int dtype, bool inverse, int64_t h, int64_t w, int levels, 
     // measured defaults (4096^2, 5 levels, cold HBM, one tile per
     // work-group, blocks dealt round-robin to the XCDs):
     //  - FP32 analysis: 32 x 256 tiles, 4 x 4 registers per thread, 512
-    //    threads, two-row wavefronts (26.0-26.2 us; level 3 by shuffles);
-    //  - FP32 synthesis of large images: 64 x 256 tiles, 8 x 4 registers per
-    //    thread, 512 threads (23.5 us against 24.4 us for 32 x 256 with
-    //    4 x 4); smaller images keep the 32-row tiles;
-    //  - 16-bit data of rows of 1024 or more: 32 x 512 tiles, 8 x 8
-    //    registers per thread, 256 threads, level 3 in registers (analysis
-    //    15.1 us against 15.9 us, synthesis 14.0 against 14.3 us); narrower
-    //    images keep the 32 x 256 analysis and 32 x 512 synthesis tiles.
-    if (dtype == 0) return inverse ? (h * w >= ((int64_t)1 << 22) ? 17 : 1) : 14;
-    if (w >= 1024) return 15;
-    return inverse ? 1 : 0;
+    //    threads, two-row wavefronts (25.0 us; level 3 by shuffles);
+    //  - FP32 synthesis: 64 x 256 tiles, 8 x 4 registers per thread, 512
+    //    threads (23.9-24.1 us against 24.5-24.8 us for 32 x 256 with
+    //    4 x 4), but only for images of whole tiles whose tile count fills
+    //    the resident work-groups an exact number of times: with partial
+    //    tiles or a last, partly filled round these large tiles lose
+    //    (4096 x 4224: 27.5 against 25.3 us; 4096 x 4352, whole tiles but
+    //    1088 of them: 27.4 against 25.0 us);
+    //  - 16-bit analysis of rows of 1024 or more: 32 x 512 tiles (BF16),
+    //    8 x 8 registers per thread, 256 threads, level 3 in registers
+    //    (13.2-13.5 us against 13.8 us for 32 x 256);
+    //  - 16-bit synthesis: the same 8 x 8 tiles for images of whole tiles
+    //    (13.5 against 14.1-14.3 us), 32 x 512 tiles of 4 x 8 otherwise
+    //    (4096 x 4224: 16.3 against 17.9 us).
+    if (dtype == 0) {
+        if (!inverse) return 14;
+        const int64_t tiles = (h / 64) * (w / 256);
+        const int64_t resident = 4 * (int64_t)device_cus();
+        const bool whole = h % 64 == 0 && w % 256 == 0 && tiles >= resident && tiles % resident == 0;
+        return whole ? 17 : 1;
+    }
+    if (!inverse) return w >= 1024 ? 15 : 0;
+    return (w >= 1024 && w % 512 == 0 && h % 32 == 0) ? 15 : 1;
 }
 
 int choose_config_1d(int dtype, bool inverse, int64_t n, int levels, int64_t batch) {

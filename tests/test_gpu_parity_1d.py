@@ -129,3 +129,40 @@ def test_chunk_configs(T, cfg, dt, n, L, what):
         _check_fwd_inv(T, dt, n, L, seed=1000 + 7 * cfg + n + L, what=f"chunk config {cfg} ({what})")
     finally:
         assert _abi.haar_force_config_1d(dt, -1) == 0
+
+
+@pytest.mark.parametrize("batch,n,L", [(1, 65536, 16), (3, 65536, 16), (8, 8192, 13), (5, 1 << 18, 18),
+                                       (2, 16384, 14), (100, 8192, 13)])
+def test_deep_fp32_batches(T, batch, n, L):
+    """Deep FP32 analyses (chunks, then the finishing kernel) of batches with
+    few and many chunks, including the 1024-sample chunks chosen for
+    latency-bound signals: every coefficient against the oracle, on three
+    calls in a row and under graph replay with eager calls in between."""
+    import torch
+    rng = np.random.default_rng(n + L + batch)
+    xs = rng.standard_normal((batch, n)).astype(np.float32)
+    ref = oracle.fwd_1d(xs.astype(np.float64), L)
+    xd = to_device(xs, G.F32)
+
+    def check(y, what):
+        yw = to_host(y, G.F32).astype(np.float64)
+        for b in range(batch):
+            check_signal(yw[b], ref[b], rms(xs[b]), G.F32, f"{what} n={n} L={L} item {b}")
+    for rep in range(3):
+        check(T.fwd1d(xd, L), f"call {rep}")
+    out = torch.empty_like(xd)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        T.fwd1d(xd, L, out=out)
+        with torch.cuda.graph(g, stream=side):
+            T.fwd1d(xd, L, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        check(out, f"replay {rep}")
+        check(T.fwd1d(xd, L), f"eager between replays {rep}")
