@@ -4,6 +4,7 @@ The transform W is orthonormal (W^T W = I), so the vector-Jacobian product of
 the analysis is its adjoint W^T = W^{-1}: the backward of the analysis is the
 synthesis bank applied to the incoming gradient, and the backward of the
 synthesis is the analysis.  Nothing is saved for backward but the level count.
+The transform calls make the incoming gradient contiguous when it is not.
 """
 from __future__ import annotations
 
@@ -20,7 +21,7 @@ class HaarFwd1D(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return T.inv1d(g.contiguous(), ctx.levels), None
+        return T.inv1d(g, ctx.levels), None
 
 
 class HaarInv1D(torch.autograd.Function):
@@ -31,7 +32,7 @@ class HaarInv1D(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return T.fwd1d(g.contiguous(), ctx.levels), None
+        return T.fwd1d(g, ctx.levels), None
 
 
 class HaarFwd2D(torch.autograd.Function):
@@ -42,7 +43,7 @@ class HaarFwd2D(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return T.inv2d(g.contiguous(), ctx.levels), None
+        return T.inv2d(g, ctx.levels), None
 
 
 class HaarInv2D(torch.autograd.Function):
@@ -53,7 +54,7 @@ class HaarInv2D(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return T.fwd2d(g.contiguous(), ctx.levels), None
+        return T.fwd2d(g, ctx.levels), None
 
 
 class HaarFwd3D(torch.autograd.Function):
@@ -64,7 +65,7 @@ class HaarFwd3D(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return T.inv3d(g.contiguous(), ctx.levels), None
+        return T.inv3d(g, ctx.levels), None
 
 
 class HaarInv3D(torch.autograd.Function):
@@ -75,7 +76,7 @@ class HaarInv3D(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return T.fwd3d(g.contiguous(), ctx.levels), None
+        return T.fwd3d(g, ctx.levels), None
 
 
 def haar_fwd1d(x, levels):
