@@ -348,8 +348,9 @@ def write_kernel_stats(stats_csv: str, command: str, out_md: str, max_rows: int 
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     total = len(rows)
     rows = rows[:max_rows]
-    trace = stats_csv.replace("_kernel_stats.csv", "_kernel_trace.csv")
-    iso = _isolated_averages(trace) if os.path.exists(trace) else {}
+    trace = stats_csv[:-len("_kernel_stats.csv")] + "_kernel_trace.csv" \
+        if stats_csv.endswith("_kernel_stats.csv") else None
+    iso = _isolated_averages(trace) if trace and os.path.exists(trace) else {}
     with open(out_md, "w") as f:
         f.write(f"# Kernel durations (rocprofv3 --kernel-trace --stats)\n\nCommand: `{command}`\n\n")
         if total > len(rows):

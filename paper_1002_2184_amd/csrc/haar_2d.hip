@@ -218,7 +218,20 @@ static hipError_t launch2d(const Pass2D& p, bool inverse, hipStream_t s) {
     if (p.persist == 0 && p.total_tiles <= kMaxGrid) {
         if (p.total_tiles <= 0) return hipSuccess;
         const unsigned grid = (unsigned)p.total_tiles;
-        // tiles that own whole cache lines read them with nontemporal loads
+        // tiles that own whole cache lines read them with nontemporal loads;
+        // 16-bit passes among them (p.pace) pace their stores: analysis
+        // outputs at most 2 operations behind, synthesis outputs 0
+        if constexpr (SX::kBytes == 2 && SD::kBytes == 2 && SL::kBytes == 2) {
+            if (p.pace) {
+                if (inverse)
+                    hipLaunchKernelGGL((inv2d_kernel<Paced<SX, 0>, SD, SL, RY, RX, GY, GX, true>), dim3(grid),
+                                       dim3(GY * GX), 0, s, p, edge, interior);
+                else
+                    hipLaunchKernelGGL((fwd2d_kernel<SX, Paced<SD, 2>, Paced<SL, 2>, RY, RX, GY, GX, MAP, true>),
+                                       dim3(grid), dim3(GY * GX), 0, s, p, edge, interior);
+                return hipGetLastError();
+            }
+        }
         if (inverse) {
             if (p.ntl)
                 hipLaunchKernelGGL((inv2d_kernel<SX, SD, SL, RY, RX, GY, GX, true>), dim3(grid), dim3(GY * GX), 0,

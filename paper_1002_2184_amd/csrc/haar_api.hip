@@ -207,6 +207,9 @@ int run_2d(const void* in, void* out, int64_t H, int64_t W, int L, int64_t batch
         // 16.9 us) and keep streaming stores.
         p.wb = !inverse && !p.ntl && p.vec_ok && tc.wg_per_cu == 0 && eb == 4 ? 1 : 0;
         if (p.wb) p.remap = 1;
+        // 16-bit passes on layouts whose tiles own whole lines pace their
+        // stores (Paced in haar_device.h)
+        p.pace = p.ntl && !mixed && eb == 2 && tc.wg_per_cu == 0 ? 1 : 0;
         hipError_t e = inverse ? launch_inv2d(p, dtype, pcfg, x_f32, ll_f32, s)
                                : launch_fwd2d(p, dtype, pcfg, x_f32, ll_f32, s);
         if (e != hipSuccess) rc = hip_error(e, inverse ? "inv2d launch" : "fwd2d launch");

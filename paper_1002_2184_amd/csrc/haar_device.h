@@ -124,6 +124,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 struct StF32 {
     static constexpr bool kStream = true;   // HBM, addressed through global pointers
     static constexpr bool kNT = true;       // outputs written with streaming stores
+    static constexpr int kPace = -1;        // stores not paced (see Paced)
     using raw = float;
     static constexpr int kBytes = 4;
     __device__ __forceinline__ static float ld(raw v) { return v; }
@@ -133,6 +134,7 @@ struct StF32 {
 struct StBF16 {
     static constexpr bool kStream = true;   // HBM, addressed through global pointers
     static constexpr bool kNT = true;       // outputs written with streaming stores
+    static constexpr int kPace = -1;        // stores not paced (see Paced)
     using raw = uint16_t;
     static constexpr int kBytes = 2;
     __device__ __forceinline__ static float ld(raw v) { return __uint_as_float((uint32_t)v << 16); }
@@ -145,6 +147,7 @@ struct StBF16 {
 struct StLds {
     static constexpr bool kStream = false;
     static constexpr bool kNT = false;
+    static constexpr int kPace = -1;
     using raw = float;
     static constexpr int kBytes = 4;
     __device__ __forceinline__ static float ld(raw v) { return v; }
@@ -154,6 +157,7 @@ struct StLds {
 struct StF16 {
     static constexpr bool kStream = true;   // HBM, addressed through global pointers
     static constexpr bool kNT = true;       // outputs written with streaming stores
+    static constexpr int kPace = -1;        // stores not paced (see Paced)
     using raw = uint16_t;
     static constexpr int kBytes = 2;
     __device__ __forceinline__ static float ld(raw v) {
@@ -248,6 +252,9 @@ __device__ __forceinline__ void ld_vec(const typename S::raw* p, float* out) {
 
 template <class S, class T>
 __device__ __forceinline__ void st_s(T v, T* p) {
+    // s_waitcnt vmcnt(kPace), the other counters left alone (gfx9 encoding:
+    // vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+    if constexpr (S::kStream && S::kPace >= 0) __builtin_amdgcn_s_waitcnt(0x0F70 | S::kPace);
     if constexpr (S::kStream && S::kNT)
         __builtin_nontemporal_store(v, (HAAR_GLOBAL T*)p);
     else if constexpr (S::kStream)
@@ -264,6 +271,20 @@ __device__ __forceinline__ void st_s(T v, T* p) {
 template <class S>
 struct WriteBack : S {
     static constexpr bool kNT = false;
+};
+
+// The same storage format with paced stores: before each store the
+// wavefront waits until at most K of its vector-memory operations are still
+// outstanding, so that a wavefront never has more than about K + 1 stores in
+// flight.  The 16-bit 2D kernels issue many narrow band stores (8 bytes and
+// less per lane); left unpaced they queue up in the write path and the whole
+// launch runs slower (4096 x 4096 BF16 L5: analysis 13.6-13.7 us unpaced,
+// 12.6-12.7 us with K = 2; synthesis 14.8-15.0 us unpaced, 13.8-13.9 us with
+// K = 0).  FP32 kernels and the plan kernels ran slower paced.
+template <class S, int K>
+struct Paced : S {
+    static_assert(K >= 0 && K < 16, "vmcnt field");
+    static constexpr int kPace = K;
 };
 
 template <class S, int N>

@@ -24,6 +24,7 @@ struct Pass2D {
     int64_t persist;                        // interior grid size (0 = one tile per work-group)
     int32_t ntl;                            // every tile owns whole cache lines: nontemporal loads
     int32_t wb;                             // analysis outputs with write-back stores (tiles share lines)
+    int32_t pace;                           // 16-bit outputs of an aligned layout: paced stores (with ntl)
 };
 
 // One fused 1D pass: `levels` levels on a length-n region (chunks of C).

@@ -11,10 +11,12 @@ pytestmark = pytest.mark.gpu
 
 DTYPES = [G.F32, G.BF16, G.F16]
 # (h, w): degenerate, single tile, multi-tile full, ragged, unaligned rows; full
-# tiles whose rows and band origins start at odd elements (W/2 or W/4 odd)
+# tiles whose rows and band origins start at odd elements (W/2 or W/4 odd);
+# wide rows of whole cache lines in every dtype (nontemporal loads, and paced
+# stores for 16-bit data)
 SHAPES = [(1, 1), (1, 9), (7, 1), (2, 2), (3, 5), (32, 32), (32, 128), (64, 256), (33, 129),
           (100, 102), (130, 70), (257, 300), (96, 520), (64, 1090), (96, 1546), (64, 1025),
-          (160, 578)]
+          (160, 578), (64, 2048)]
 
 
 def _levels_for(h, w):
