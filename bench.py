@@ -546,6 +546,42 @@ def suite():
     res["unit_elements_per_s"] = "G elements/s, fwd + bwd"
     print(json.dumps(res), flush=True)
 
+    # 4b) the plain 2D kernels on the 4096^2 image, 5 levels, in 16-bit
+    #     storage: each kernel's duration under the headline protocol (16
+    #     rotating sets, start event queued behind 16 untimed launches)
+    from paper_1002_2184_amd import _abi
+    x0 = torch.from_numpy(G.config2()).to(dev)
+    for name, dt, code in (("bf16", torch.bfloat16, 1), ("f16", torch.float16, 2)):
+        xs16 = [x0.to(dt) for _ in range(16)]
+        ys16 = [torch.empty_like(v) for v in xs16]
+        zs16 = [torch.empty_like(v) for v in xs16]
+        q = st.cuda_stream
+
+        def per_launch(fn, reps=400):
+            for k in range(16):
+                fn(k)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for k in range(reps):
+                fn(k % 16)
+            e1.record(st)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+        us_f = 1e3 * per_launch(lambda k: _abi.check(_abi.haar_fwd_2d(
+            xs16[k].data_ptr(), ys16[k].data_ptr(), H, W, LEVELS, 1, code, q)))
+        us_i = 1e3 * per_launch(lambda k: _abi.check(_abi.haar_inv_2d(
+            ys16[k].data_ptr(), zs16[k].data_ptr(), H, W, LEVELS, 1, code, q)))
+        nb = 2 * H * W * 2
+        print(json.dumps({"workload": f"2d-smooth-4096x4096-L5 {name} kernels", "us_fwd": round(us_f, 2),
+                          "us_inv": round(us_i, 2), "gbps_fwd": round(nb / (us_f * 1e-6) / 1e9, 1),
+                          "gbps_inv": round(nb / (us_i * 1e-6) / 1e9, 1),
+                          "roundtrip_max_err_over_rms": float((zs16[0].float() - xs16[0].float()).abs().max()
+                                                              / xs16[0].float().pow(2).mean().sqrt())}),
+              flush=True)
+        del xs16, ys16, zs16
+    del x0
+    torch.cuda.empty_cache()
+
     # 5) fused shrinkage (analysis -> soft threshold -> synthesis in one HBM
     #    pass) on the 4096^2 image, 5 levels, 16 rotating sets; beside the
     #    same pipeline unfused: fwd2d, torch elementwise threshold, inv2d
