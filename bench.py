@@ -558,8 +558,8 @@ def suite():
         q = st.cuda_stream
 
         def per_launch(fn, reps=400):
-            for k in range(16):
-                fn(k)
+            for k in range(128):
+                fn(k % 16)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(st)
             for k in range(reps):
@@ -894,15 +894,18 @@ def main():
     # average duration of each kernel: back-to-back launches of it alone,
     # bracketed by HIP events on the launch stream (the sets still rotate, so
     # every launch reads data last touched 15 launches earlier).  The start
-    # event is queued behind 16 untimed launches, so that the timed ones are
-    # already queued when it fires: the figure is the kernel's duration, not
-    # the latency of a first launch on an idle device.  At least 200 launches.
+    # event is queued behind 128 untimed launches (about 3 ms of work): the
+    # timed ones are already queued when it fires, and the device has left
+    # the slower state it runs in for the first milliseconds of sustained
+    # work (the same kernel measured 0.5-0.7 us longer when it was the first
+    # thing timed).  The figure is the kernel's steady-state duration.  At
+    # least 200 launches.
     def per_launch_ms(fn):
         reps = max(args.steps, 200)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        for k in range(16):
+        for k in range(128):
             fn(k % SETS)
         e0.record(stream)
         for k in range(reps):
