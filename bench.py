@@ -27,6 +27,7 @@ import hashlib
 import json
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -894,29 +895,38 @@ def main():
     # average duration of each kernel: back-to-back launches of it alone,
     # bracketed by HIP events on the launch stream (the sets still rotate, so
     # every launch reads data last touched 15 launches earlier).  The start
-    # event is queued behind 128 untimed launches (about 3 ms of work): the
+    # event is queued behind 512 untimed launches (about 13 ms of work): the
     # timed ones are already queued when it fires, and the device has left
-    # the slower state it runs in for the first milliseconds of sustained
-    # work (the same kernel measured 0.5-0.7 us longer when it was the first
-    # thing timed).  The figure is the kernel's steady-state duration.  At
-    # least 200 launches.
+    # the slower state it runs in for the first several milliseconds of
+    # sustained work (the same kernel measured 0.5-0.7 us longer when it was
+    # the first thing timed, and still 0.5 us longer after 5 ms of work).
+    # The figure is the kernel's steady-state duration.  At
+    # least 200 launches, in 10 blocks with an event between blocks: the
+    # average over all of them, and the 10th / 50th / 90th percentile of the
+    # block averages (us).
     def per_launch_ms(fn):
-        reps = max(args.steps, 200)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        blocks = 10
+        per = max(args.steps, 200) // blocks
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(blocks + 1)]
         torch.cuda.synchronize()
-        for k in range(128):
+        for k in range(512):
             fn(k % SETS)
-        e0.record(stream)
-        for k in range(reps):
-            fn(k % SETS)
-        e1.record(stream)
+        ev[0].record(stream)
+        for b in range(blocks):
+            for k in range(per):
+                fn((b * per + k) % SETS)
+            ev[b + 1].record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        means = sorted(ev[b].elapsed_time(ev[b + 1]) / per * 1e3 for b in range(blocks))
+        spread = {"p10": round(means[1], 3), "p50": round(statistics.median(means), 3),
+                  "p90": round(means[-2], 3)}
+        return ev[0].elapsed_time(ev[-1]) / (blocks * per), spread
 
     q0 = stream.cuda_stream
-    fwd_avg = per_launch_ms(lambda s: _abi.check(_abi.haar_fwd_2d(xp[s], yp[s], H, W, LEVELS, 1, 0, q0)))
-    inv_avg = per_launch_ms(lambda s: _abi.check(_abi.haar_inv_2d(yp[s], zp[s], H, W, LEVELS, 1, 0, q0)))
+    fwd_avg, fwd_spread = per_launch_ms(
+        lambda s: _abi.check(_abi.haar_fwd_2d(xp[s], yp[s], H, W, LEVELS, 1, 0, q0)))
+    inv_avg, inv_spread = per_launch_ms(
+        lambda s: _abi.check(_abi.haar_inv_2d(yp[s], zp[s], H, W, LEVELS, 1, 0, q0)))
 
     # correctness spot check of the timed outputs (GPU side)
     rt_err = float((zs[0] - xs[0]).abs().max() / xs[0].pow(2).mean().sqrt())
@@ -1017,6 +1027,7 @@ def main():
                      "avg_launch_us": round(dom_ms * 1e3, 3),
                      "bytes_per_launch": int(alg_launch)},
         "kernels_avg_us": {"fwd2d": round(fwd_avg * 1e3, 3), "inv2d": round(inv_avg * 1e3, 3)},
+        "kernels_block_us": {"fwd2d": fwd_spread, "inv2d": inv_spread},
         "fwd_bwd": {"value": round(ag_gbps, 2), "unit": "GB/s", "ms_per_step": round(ag_ms, 5),
                     "vs_plain_fwd_inv": round(ag_gbps / gbps, 4),
                     "how": f"HaarFwd2D.apply + torch.autograd.grad on each buffer set, the steps round-robin on "
