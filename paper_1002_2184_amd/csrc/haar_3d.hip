@@ -18,7 +18,9 @@
 // wavefront through LDS.  Edge tiles (and odd counts) run a generic path
 // that takes whole 2 x 2 x 2 blocks per thread, level by level, with the
 // carry rule on each axis and only the LLL regions in LDS.  Deeper
-// transforms chain passes through scratch.
+// transforms chain passes through scratch; when the region left by the
+// first pass is small, all the remaining levels run in one tail launch of
+// one work-group per volume.
 //
 // Arithmetic: samples are widened to FP64, which gfx950 executes at the
 // rate of unpacked FP32.  One FP64 add replaces the six-operation pair sum
@@ -766,6 +768,185 @@ hipError_t launch3_s(const Pass3D& p, bool inverse, bool rdf, bool ldf, hipStrea
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Tail of a deep transform: every level after the first pass, in one launch
+// of one work-group per item.  After three levels a volume's LLL region is
+// small (a 256^3 volume leaves 32^3), and chained passes over it cost a
+// launch and a half-empty tile grid per three levels.  The work-group walks
+// the region level by level over the level's 2 x 2 x 2 blocks (carry rule
+// on each axis), keeps each level's LLL region in LDS (odd levels in A, even
+// levels in B) and writes the detail octants to their packed positions.
+// The region comes from (analysis) or goes to (synthesis) the first pass's
+// FP64 scratch; the deepest LLL is the call's own output / input.
+// ---------------------------------------------------------------------------
+constexpr int kTailThreads = 1024;
+constexpr int kTailA = 4096, kTailB = 512;     // LDS doubles: LLL after the tail's level 1 / 2
+
+struct Tail3D {
+    // the region after the first pass (FP64 scratch, dense per item)
+    double* reg; int64_t reg_b;
+    void* det; int64_t det_p, det_r, det_b;    // the call's packed buffer (storage type)
+    int64_t d, h, w;                           // region
+    int32_t levels;                            // levels of the tail
+};
+
+// Can the tail of a region of d x h x w run in one work-group per item?
+inline bool tail_fits(int64_t d, int64_t h, int64_t w) {
+    const int64_t a = ceil_shift_host(d, 1) * ceil_shift_host(h, 1) * ceil_shift_host(w, 1);
+    const int64_t b = ceil_shift_host(d, 2) * ceil_shift_host(h, 2) * ceil_shift_host(w, 2);
+    return a <= kTailA && b <= kTailB;
+}
+
+// Block grid of level j of the tail: the level-(j-1) region and its blocks.
+struct TailLevel {
+    int nz, ny, nx, bz_n, by_n, bx_n, nb;
+    __device__ __forceinline__ TailLevel(const Tail3D& t, int j) {
+        nz = (int)ceil_shift(t.d, j - 1);
+        ny = (int)ceil_shift(t.h, j - 1);
+        nx = (int)ceil_shift(t.w, j - 1);
+        bz_n = (nz + 1) >> 1;
+        by_n = (ny + 1) >> 1;
+        bx_n = (nx + 1) >> 1;
+        nb = bz_n * by_n * bx_n;
+    }
+};
+
+constexpr int kTailSlots = kTailA / kTailThreads;   // blocks per thread at the tail's level 1
+
+template <class S>
+__global__ __launch_bounds__(kTailThreads) void fwd3d_tail_kernel(Tail3D t) {
+    __shared__ double bufA[kTailA], bufB[kTailB];
+    using raw = typename S::raw;
+    const int64_t item = blockIdx.x;
+    const double* reg = t.reg + item * t.reg_b;
+    raw* det = reinterpret_cast<raw*>(t.det) + item * t.det_b;
+    Pass3D p{};
+    p.d = t.d;
+    p.h = t.h;
+    p.w = t.w;
+    p.det_p = t.det_p;
+    p.det_r = t.det_r;
+    for (int j = 1; j <= t.levels; ++j) {
+        const TailLevel G(t, j);
+        const double* in = (j - 1) & 1 ? bufA : bufB;
+        double* out = j & 1 ? bufA : bufB;
+        const Level3 Lj = level_sizes(p, j);
+        for (int s = threadIdx.x; s < G.nb; s += kTailThreads) {
+            const int bx = s % G.bx_n, by = (s / G.bx_n) % G.by_n, bz = s / (G.bx_n * G.by_n);
+            const bool fx = 2 * bx + 1 < G.nx, fy = 2 * by + 1 < G.ny, fz = 2 * bz + 1 < G.nz;
+            double q[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+                q[c] = 0.0;
+                if ((dx && !fx) || (dy && !fy) || (dz && !fz)) continue;
+                const int64_t o = ((int64_t)(2 * bz + dz) * G.ny + 2 * by + dy) * G.nx + 2 * bx + dx;
+                q[c] = j == 1 ? reg[o] : in[o];
+            }
+            block_fwd(q, fx, fy, fz);
+#pragma unroll
+            for (int code = 1; code < 8; ++code)
+                if ((!(code & 1) || fx) && (!(code & 2) || fy) && (!(code & 4) || fz))
+                    st1_cached<S>(det + octant_pos(p, Lj, j, code, 0, 0, 0, bz, by, bx), (float)q[code]);
+            if (j == t.levels)
+                st1_cached<S>(det + (int64_t)bz * t.det_p + (int64_t)by * t.det_r + bx, (float)q[0]);
+            else
+                out[(bz * G.by_n + by) * G.bx_n + bx] = q[0];
+        }
+        __syncthreads();
+    }
+}
+
+// The detail coefficients of this thread's blocks of tail level j (zero
+// where the carry rule leaves no partner).
+template <class S>
+__device__ __forceinline__ void tail_details(const Tail3D& t, const Pass3D& p, const typename S::raw* det, int j,
+                                             float (&dv)[kTailSlots][7]) {
+    const TailLevel G(t, j);
+    const Level3 Lj = level_sizes(p, j);
+#pragma unroll
+    for (int k = 0; k < kTailSlots; ++k) {
+        const int s = threadIdx.x + kTailThreads * k;
+#pragma unroll
+        for (int code = 1; code < 8; ++code) dv[k][code - 1] = 0.0f;
+        if (s >= G.nb) continue;
+        const int bx = s % G.bx_n, by = (s / G.bx_n) % G.by_n, bz = s / (G.bx_n * G.by_n);
+        const bool fx = 2 * bx + 1 < G.nx, fy = 2 * by + 1 < G.ny, fz = 2 * bz + 1 < G.nz;
+#pragma unroll
+        for (int code = 1; code < 8; ++code)
+            if ((!(code & 1) || fx) && (!(code & 2) || fy) && (!(code & 4) || fz))
+                dv[k][code - 1] = ld1<S>(det + octant_pos(p, Lj, j, code, 0, 0, 0, bz, by, bx));
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(kTailThreads) void inv3d_tail_kernel(Tail3D t) {
+    __shared__ double bufA[kTailA], bufB[kTailB];
+    using raw = typename S::raw;
+    const int64_t item = blockIdx.x;
+    double* reg = t.reg + item * t.reg_b;
+    const raw* det = reinterpret_cast<const raw*>(t.det) + item * t.det_b;
+    Pass3D p{};
+    p.d = t.d;
+    p.h = t.h;
+    p.w = t.w;
+    p.det_p = t.det_p;
+    p.det_r = t.det_r;
+    // the details of level j - 1 are read while level j is undone, so each
+    // level waits on LDS and not on a fresh round of HBM reads
+    float cur[kTailSlots][7], nxt[kTailSlots][7];
+    tail_details<S>(t, p, det, t.levels, cur);
+    for (int j = t.levels; j >= 1; --j) {
+        if (j > 1) tail_details<S>(t, p, det, j - 1, nxt);
+        const TailLevel G(t, j);
+        const double* in = j & 1 ? bufA : bufB;               // LLL of level j
+        double* out = (j - 1) & 1 ? bufA : bufB;              // LLL of level j - 1
+#pragma unroll
+        for (int k = 0; k < kTailSlots; ++k) {
+            const int s = threadIdx.x + kTailThreads * k;
+            if (s >= G.nb) continue;
+            const int bx = s % G.bx_n, by = (s / G.bx_n) % G.by_n, bz = s / (G.bx_n * G.by_n);
+            const bool fx = 2 * bx + 1 < G.nx, fy = 2 * by + 1 < G.ny, fz = 2 * bz + 1 < G.nz;
+            double q[8];
+            q[0] = j == t.levels ? (double)ld1<S>(det + (int64_t)bz * t.det_p + (int64_t)by * t.det_r + bx)
+                                 : in[(bz * G.by_n + by) * G.bx_n + bx];
+#pragma unroll
+            for (int code = 1; code < 8; ++code) q[code] = (double)cur[k][code - 1];
+            block_inv(q, fx, fy, fz);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+                if ((dx && !fx) || (dy && !fy) || (dz && !fz)) continue;
+                const int64_t o = ((int64_t)(2 * bz + dz) * G.ny + 2 * by + dy) * G.nx + 2 * bx + dx;
+                if (j == 1)
+                    reg[o] = q[c];
+                else
+                    out[o] = q[c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kTailSlots; ++k)
+#pragma unroll
+            for (int c = 0; c < 7; ++c) cur[k][c] = nxt[k][c];
+    }
+}
+
+hipError_t launch_tail3d(const Tail3D& t, int64_t batch, int dtype, bool inverse, hipStream_t s) {
+    const dim3 g((unsigned)batch), b(kTailThreads);
+    if (dtype == HAAR_F32) {
+        if (inverse) hipLaunchKernelGGL(inv3d_tail_kernel<StF32>, g, b, 0, s, t);
+        else hipLaunchKernelGGL(fwd3d_tail_kernel<StF32>, g, b, 0, s, t);
+    } else if (dtype == HAAR_BF16) {
+        if (inverse) hipLaunchKernelGGL(inv3d_tail_kernel<StBF16>, g, b, 0, s, t);
+        else hipLaunchKernelGGL(fwd3d_tail_kernel<StBF16>, g, b, 0, s, t);
+    } else {
+        if (inverse) hipLaunchKernelGGL(inv3d_tail_kernel<StF16>, g, b, 0, s, t);
+        else hipLaunchKernelGGL(fwd3d_tail_kernel<StF16>, g, b, 0, s, t);
+    }
+    return hipGetLastError();
+}
+
 struct Region3D {
     int64_t d, h, w;
     int levels;
@@ -787,23 +968,47 @@ int run_3d(const void* in, void* out, int64_t D, int64_t H, int64_t W, int L, in
             left -= lp;
         }
     }
+    // the levels after the first pass run as one tail launch when the
+    // region left by the first pass is small enough for one work-group
+    const bool tail = ps.size() > 1 && tail_fits(ps[1].d, ps[1].h, ps[1].w);
+    const Region3D rt = tail ? Region3D{ps[1].d, ps[1].h, ps[1].w, L - ps[0].levels} : Region3D{};
+    if (tail) ps.resize(1);
     const int np = (int)ps.size();
     // FP64 scratch between passes: two ping-pong buffers sized for the
-    // region after the first pass
+    // region after the first pass (one when the tail follows that pass)
     void* scratch = nullptr;
     int64_t half = 0;
-    if (np > 1) {
-        half = batch * ps[1].d * ps[1].h * ps[1].w;
-        hipError_t e = hipMallocAsync(&scratch, (size_t)(2 * half * (int64_t)sizeof(double)), s);
+    if (np > 1 || tail) {
+        half = tail ? batch * rt.d * rt.h * rt.w : batch * ps[1].d * ps[1].h * ps[1].w;
+        const int nbuf = tail ? 1 : 2;
+        hipError_t e = hipMallocAsync(&scratch, (size_t)(nbuf * half * (int64_t)sizeof(double)), s);
         if (e != hipSuccess) return hip_error(e, "hipMallocAsync (3D pass scratch)");
     }
-    auto buf = [&](int k) -> void* { return (char*)scratch + ((k & 1) ? 0 : half) * (int64_t)sizeof(double); };
+    auto buf = [&](int k) -> void* {
+        return (char*)scratch + ((tail || (k & 1)) ? 0 : half) * (int64_t)sizeof(double);
+    };
+    auto run_tail = [&]() -> int {
+        Tail3D t{};
+        t.reg = reinterpret_cast<double*>(scratch);
+        t.reg_b = rt.d * rt.h * rt.w;
+        t.det = const_cast<void*>(inverse ? in : (const void*)out);
+        t.det_p = H * W;
+        t.det_r = W;
+        t.det_b = D * H * W;
+        t.d = rt.d;
+        t.h = rt.h;
+        t.w = rt.w;
+        t.levels = rt.levels;
+        hipError_t e = launch_tail3d(t, batch, dtype, inverse, s);
+        return e == hipSuccess ? HAAR_OK : hip_error(e, inverse ? "inv3d tail launch" : "fwd3d tail launch");
+    };
 
     int rc = HAAR_OK;
+    if (tail && inverse) rc = run_tail();
     for (int step = 0; step < np && rc == HAAR_OK; ++step) {
         const int k = inverse ? np - 1 - step : step;
         const Region3D& r = ps[k];
-        const bool rdf = k > 0, ldf = k < np - 1;
+        const bool rdf = k > 0, ldf = k < np - 1 || tail;
         Pass3D p{};
         p.d = r.d;
         p.h = r.h;
@@ -819,10 +1024,11 @@ int run_3d(const void* in, void* out, int64_t D, int64_t H, int64_t W, int L, in
         const int64_t rb = k == 0 ? D * H * W : r.d * r.h * r.w;
         const int64_t nd = ceil_shift_host(r.d, r.levels), nh = ceil_shift_host(r.h, r.levels);
         const int64_t nw = ceil_shift_host(r.w, r.levels);
-        p.ll = k == np - 1 ? (void*)(inverse ? in : out) : buf(k + 1);
-        p.ll_p = k == np - 1 ? H * W : nh * nw;
-        p.ll_r = k == np - 1 ? W : nw;
-        p.ll_b = k == np - 1 ? D * H * W : nd * nh * nw;
+        const bool ll_out = k == np - 1 && !tail;   // the pass's LLL is the call's deepest band
+        p.ll = ll_out ? (void*)(inverse ? in : out) : buf(k + 1);
+        p.ll_p = ll_out ? H * W : nh * nw;
+        p.ll_r = ll_out ? W : nw;
+        p.ll_b = ll_out ? D * H * W : nd * nh * nw;
         if (inverse) {
             p.dst = rptr; p.dst_p = rp; p.dst_r = rr; p.dst_b = rb;
         } else {
@@ -847,6 +1053,7 @@ int run_3d(const void* in, void* out, int64_t D, int64_t H, int64_t W, int L, in
         else e = launch3_s<StF16>(p, inverse, rdf, ldf, s);
         if (e != hipSuccess) rc = hip_error(e, inverse ? "inv3d launch" : "fwd3d launch");
     }
+    if (tail && !inverse && rc == HAAR_OK) rc = run_tail();
     if (scratch) {
         hipError_t e = hipFreeAsync(scratch, s);
         if (e != hipSuccess && rc == HAAR_OK) rc = hip_error(e, "hipFreeAsync");
