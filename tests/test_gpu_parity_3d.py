@@ -87,9 +87,13 @@ def test_fwd_inv_3d(T, dt, shape, L):
         check_roundtrip(x2[b], xw[b], dt, f"round trip {shape} L={L} item {b}")
 
 
+# The levels after the first pass run in one tail launch when the region
+# left by that pass is small; the last two shapes leave regions too large for
+# it (33 x 32 x 32 and 4 x 4 x 2049), so chained passes over scratch run there.
 DEEP = [(G.F32, (64, 64, 64), 6), (G.F32, (40, 48, 200), 8), (G.F32, (16, 16, 1024), 10),
         (G.F32, (72, 24, 136), 5), (G.F32, (64, 64, 512), 4), (G.F32, (80, 72, 704), 5),
-        (G.BF16, (64, 64, 512), 4), (G.F16, (72, 24, 136), 5), (G.BF16, (64, 64, 1024), 6)]
+        (G.BF16, (64, 64, 512), 4), (G.F16, (72, 24, 136), 5), (G.BF16, (64, 64, 1024), 6),
+        (G.F32, (264, 256, 256), 7), (G.BF16, (32, 32, 16392), 4)]
 
 
 @pytest.mark.parametrize("dt,shape,L", DEEP, ids=lambda v: str(v))
