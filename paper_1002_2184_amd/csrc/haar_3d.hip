@@ -968,9 +968,10 @@ int run_3d(const void* in, void* out, int64_t D, int64_t H, int64_t W, int L, in
             left -= lp;
         }
     }
-    // the levels after the first pass run as one tail launch when the
-    // region left by the first pass is small enough for one work-group
-    const bool tail = ps.size() > 1 && tail_fits(ps[1].d, ps[1].h, ps[1].w);
+    // the levels after the first pass run as one tail launch (one
+    // work-group per item) when the region left by the first pass is small
+    // enough for one work-group and the items fit one grid
+    const bool tail = ps.size() > 1 && tail_fits(ps[1].d, ps[1].h, ps[1].w) && batch <= ((int64_t)1 << 30);
     const Region3D rt = tail ? Region3D{ps[1].d, ps[1].h, ps[1].w, L - ps[0].levels} : Region3D{};
     if (tail) ps.resize(1);
     const int np = (int)ps.size();
