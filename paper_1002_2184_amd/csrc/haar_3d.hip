@@ -925,10 +925,12 @@ __global__ __launch_bounds__(kTailThreads) void inv3d_tail_kernel(Tail3D t) {
             }
         }
         __syncthreads();
+        if (j > 1) {
 #pragma unroll
-        for (int k = 0; k < kTailSlots; ++k)
+            for (int k = 0; k < kTailSlots; ++k)
 #pragma unroll
-            for (int c = 0; c < 7; ++c) cur[k][c] = nxt[k][c];
+                for (int c = 0; c < 7; ++c) cur[k][c] = nxt[k][c];
+        }
     }
 }
 
