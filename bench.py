@@ -166,15 +166,20 @@ PMC_KINDS = {
 }
 
 
+# raw profiler output (counter CSVs, per-kind algorithmic bytes) lives in
+# this folder of the repository, beside the rocprofv3 output directories
+RAW_DIR = os.path.join(ROOT, "gpurun_out")
+
+
 def _alg_file(kind: str) -> str:
-    return os.path.join(ROOT, "gpurun_out", f"pmc_{kind}_alg.json")
+    return os.path.join(RAW_DIR, f"pmc_{kind}_alg.json")
 
 
 def pmc_probe_kind(kind: str):
     """Dispatches for the counter passes of one of PMC_KINDS: a 64 MiB device
     copy (the calibration reference), then 4 launches of each kernel of the
     workload.  Writes the algorithmic bytes of one dispatch of each kernel
-    class to gpurun_out/pmc_<kind>_alg.json for the summary."""
+    class to pmc_<kind>_alg.json in the raw-output folder for the summary."""
     import numpy as np
     import torch
     from paper_1002_2184_amd import plan as PL
@@ -820,7 +825,7 @@ def main():
         pmc_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the transform shards by batch items or row stripes without communication; "
               "see the design notes)", file=sys.stderr)
         sys.exit(2)

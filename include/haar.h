@@ -96,7 +96,7 @@ typedef enum {
     HAAR_ERR_WORKSPACE = 6,   /* workspace NULL, too small or misaligned           */
     HAAR_ERR_HIP = 7,         /* a HIP runtime call failed (see haar_last_error)   */
     HAAR_ERR_PLAN = 8,        /* NULL / not uploaded plan, or an invalid plan item */
-    HAAR_ERR_UNSUPPORTED = 9, /* valid arguments this build does not implement     */
+    HAAR_ERR_UNSUPPORTED = 9, /* valid arguments the library does not implement    */
     HAAR_ERR_ARG = 10         /* an argument value is invalid (mode, threshold)    */
 } haar_status;
 
