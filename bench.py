@@ -163,6 +163,9 @@ PMC_KINDS = {
     "bf16_4096": "fwd2d / inv2d kernels, 4096x4096 BF16, 5 levels, 16 rotating sets",
     "plans_cfg5": "2D plans of the 512 uneven images, 4 levels, fwd and bwd, in BF16 and in FP32",
     "plans_cfg3": "1D plans of the 1024 uneven sine-mix signals, full depth, fwd and inv, FP32",
+    "fused": "fused one-pass kernels, FP32: soft shrinkage of the 4096x4096 image (L5) and of "
+             "256 x 65536 signals (L12), the sparsity-loss training step on 192 x 512^2 (L3)",
+    "volumes": "3D kernels on the 4 x 256^3 phantom volumes, 3 levels, fwd and inv, FP32 and BF16",
 }
 
 
@@ -237,6 +240,39 @@ def pmc_probe_kind(kind: str):
         nb = 2 * sum(v.numel() for v in xs) * 4
         alg = {"plan1d fwd f32": nb, "plan1d inv f32": nb,
                "finish1d f32": 0}
+    elif kind == "fused":
+        x0 = torch.from_numpy(G.config2(H, W)).to(dev)
+        xs = [x0.clone() for _ in range(4)]
+        ys = [torch.empty_like(x0) for _ in range(4)]
+        for k in range(4):
+            T.shrink2d(xs[k], 5, [40.0, 20.0, 10.0, 5.0, 2.5], "soft", out=ys[k])
+        del xs, ys
+        x1 = [torch.randn(256, 65536, device=dev) for _ in range(4)]
+        y1 = [torch.empty_like(v) for v in x1]
+        for k in range(4):
+            T.shrink1d(x1[k], 12, 0.5, "soft", out=y1[k])
+        del x1, y1
+        xa = [torch.randn(64 * 3, 512, 512, device=dev) for _ in range(2)]
+        ga = [torch.empty_like(v) for v in xa]
+        for k in range(4):
+            T.l1_grad2d(xa[k % 2], 3, out=ga[k % 2])
+        alg = {"shrink2d f32": 2 * H * W * 4, "shrink1d f32": 2 * 256 * 65536 * 4,
+               "l1grad2d f32": 2 * 64 * 3 * 512 * 512 * 4, "l1 loss reduce": 0}
+        del xa, ga
+    elif kind == "volumes":
+        vol = torch.from_numpy(G.to_storage(G.phantom_volume(G.rng_for(8), 256, 256, 256), G.F32)).to(dev)
+        for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+            vs = [vol.expand(4, 256, 256, 256).contiguous().to(dt) for _ in range(2)]
+            cs = [torch.empty_like(v) for v in vs]
+            for k in range(4):
+                T.fwd3d(vs[k % 2], 3, out=cs[k % 2])
+            for k in range(4):
+                T.inv3d(cs[k % 2], 3, out=vs[(k + 1) % 2])
+            nb = 2 * vs[0].numel() * vs[0].element_size()
+            alg[f"fwd3d {name}"] = nb
+            alg[f"inv3d {name}"] = nb
+            del vs, cs
+            torch.cuda.empty_cache()
     else:
         raise SystemExit(f"unknown counter probe {kind!r}; one of {sorted(PMC_KINDS)}")
     torch.cuda.synchronize()
@@ -269,6 +305,19 @@ def _kernel_class(name: str):
     m = re.search(r"(finish1d\w*|plan1d_finish_kernel)<([^>]*)>", name)
     if m:
         return f"finish1d {dtype_of(m.group(2))}"
+    m = re.search(r"shrink2d_\w*kernel<([^>]*)>", name)
+    if m:
+        a = [x.strip() for x in m.group(1).split(",")]
+        return f"{'l1grad2d' if a[3] == '1' else 'shrink2d'} {dtype_of(m.group(1))}"
+    m = re.search(r"shrink1d_\w*kernel<([^>]*)>", name)
+    if m:
+        return f"shrink1d {dtype_of(m.group(1))}"
+    if "l1_loss_reduce_kernel" in name:
+        return "l1 loss reduce"
+    for k in ("fwd3d", "inv3d"):
+        m = re.search(k + r"_\w*kernel<([^>]*)>", name)
+        if m:
+            return f"{k} {dtype_of(m.group(1))}"
     for k in ("fwd2d", "inv2d"):
         m = re.search(k + r"\w*kernel<([^>]*)>", name)
         if m:
