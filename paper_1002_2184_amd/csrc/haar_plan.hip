@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <numeric>
 #include <type_traits>
@@ -289,10 +290,25 @@ bool overlap(const void* a, const void* b, uint64_t bytes) {
     return x < y + bytes && y < x + bytes;
 }
 
+// LDS bytes per compute unit of the current device (cached per device)
+int device_lds_per_cu() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 160 * 1024;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+            n <= 0)
+            n = 160 * 1024;
+        cache[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 template <class K>
-int grid_for(K kernel, int threads) {
+int grid_for(K kernel, int threads, size_t lds_pad = 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds_pad) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu * device_cus();
@@ -316,14 +332,29 @@ hipError_t launch_plan2d(const haar_plan* pl, void* ws, hipStream_t s, bool quer
     const PlanTile2D* tiles = (const PlanTile2D*)ws_at(ws, pl->off_units);
     unsigned* ctr = (unsigned*)ws;
     const unsigned n = (unsigned)pl->nunits;
+    const bool inv = pl->inverse != 0;
+    // FP32 synthesis plans in 512-thread tiles run at most three work-groups
+    // per CU: LDS that the kernel never touches, allocated at launch, caps
+    // the occupancy (the 512 uneven images in FP32: 1.07 -> 1.02 ms).  The
+    // analyses did not gain, and the 16-bit plans (256-thread tiles) ran
+    // slower capped at 4, 3 or 2 per CU.
+    auto lds_pad = [&](int threads, size_t stat) -> size_t {
+        if (!inv || S::kBytes != 4 || threads != 512) return 0;
+        const size_t want = (size_t)device_lds_per_cu() / 4 + 256;   // three fit in a CU, four do not
+        return want > stat ? want - stat : 0;
+    };
     auto go = [&](auto kernel, int threads) -> hipError_t {
-        const int g = unit_grid(pl, n, grid_for(kernel, threads));
+        hipFuncAttributes fa{};
+        const size_t stat = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) == hipSuccess
+                                ? fa.sharedSizeBytes
+                                : 0;
+        const size_t pad = lds_pad(threads, stat);
+        const int g = unit_grid(pl, n, grid_for(kernel, threads, pad));
         if (grid) *grid = g;
         if (query_only) return hipSuccess;
-        hipLaunchKernelGGL(kernel, dim3(g), dim3(threads), 0, s, items, tiles, n, ctr);
+        hipLaunchKernelGGL(kernel, dim3(g), dim3(threads), pad, s, items, tiles, n, ctr);
         return hipGetLastError();
     };
-    const bool inv = pl->inverse != 0;
     // schedules: 0 strided walk, 1 claiming, 2 one unit per work-group,
     // 3 the same XCD-contiguous with write-back stores, 4 XCD-contiguous
 #define HAAR_PLAN2D_GO(GY_, GX_, DYN_, RM_, WB_)                                               \
